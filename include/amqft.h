@@ -1,0 +1,159 @@
+/*
+ * amqft -- batched power-of-two complex DFT by the AM-QFT recursion on AMD
+ * MI355X (gfx950).  C ABI: plain pointers and sizes, status codes, no
+ * exceptions, no printing.
+ *
+ * Method: L. Pasquini, "A class of AM-QFT algorithms for power-of-two FFT"
+ * (arXiv:1404.1810).  The transform computed is the CDFT of eq. qft_0A,
+ *
+ *     X(k) = sum_{n=0}^{N-1} x(n) exp(-i 2 pi n k / N),   k = 0..N-1,
+ *
+ * unnormalised, with input and output in natural ("growing") order
+ * (Sec. 2.4, Table tab:implementation).  The eight variants of Sec. 5-6 are
+ * selected by amqft_variant; all of them compute the same DFT and differ only
+ * in rounding (Sec. 7.3).  N = 1 (identity) is accepted as an extension; the
+ * paper's recursion starts at N = 2 (Sec. 4).
+ *
+ * Memory layout: complex values are interleaved (re, im) pairs of the storage
+ * type; every signal is contiguous.  Device pointers come from the caller
+ * (hipMalloc, or torch.empty(..., device="cuda") on ROCm) and must stay valid
+ * until the work queued on the stream has completed.  in == out (in place) is
+ * allowed for every entry point below unless stated otherwise.
+ *
+ * Errors: every entry point validates its arguments before any HIP call and
+ * returns AMQFT_ERR_INVALID_ARG / AMQFT_ERR_NOT_POW2 / AMQFT_ERR_UNSUPPORTED
+ * without touching the GPU; AMQFT_ERR_ALLOC reports a failed device
+ * allocation and AMQFT_ERR_HIP a failed launch or copy (the HIP error string
+ * is kept per thread and returned by amqft_last_hip_error()).
+ */
+#ifndef AMQFT_H
+#define AMQFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Variant = skeleton x odd-to-even conversion M1..M8 (Sec. 5, Sec. 6):
+ * 1, 4, 5, 8 split time indices first (dct_ot/dst_ot functions); 2, 3, 6, 7
+ * split harmonics first (dct_to/dst_to).  4 is the improved QFT. */
+typedef enum {
+    AMQFT_V1 = 1, AMQFT_V2 = 2, AMQFT_V3 = 3, AMQFT_V4 = 4,
+    AMQFT_V5 = 5, AMQFT_V6 = 6, AMQFT_V7 = 7, AMQFT_V8 = 8
+} amqft_variant;
+
+/* Storage type of the complex data; arithmetic is FP64 for AMQFT_C128 and
+ * FP32 for the other three. */
+typedef enum {
+    AMQFT_C128 = 0, /* complex double: 16 bytes per point            */
+    AMQFT_C64 = 1,  /* complex float: 8 bytes per point              */
+    AMQFT_C32H = 2, /* FP16 (re, im) pairs, FP32 arithmetic: 4 bytes */
+    AMQFT_C32B = 3  /* BF16 (re, im) pairs, FP32 arithmetic: 4 bytes */
+} amqft_dtype;
+
+typedef enum {
+    AMQFT_OK = 0,
+    AMQFT_ERR_INVALID_ARG = 1, /* null pointer, bad enum, bad batch/offsets */
+    AMQFT_ERR_NOT_POW2 = 2,    /* a length is not a power of two or is < 1  */
+    AMQFT_ERR_UNSUPPORTED = 3, /* length above AMQFT_MAX_LOG2N, or a flag
+                                  combination this build does not provide   */
+    AMQFT_ERR_ALLOC = 4,       /* device or host allocation failed          */
+    AMQFT_ERR_HIP = 5          /* a HIP call failed                         */
+} amqft_status;
+
+/* Plan flags. */
+enum {
+    /* Generate the trigonometric constants (Sec. 7.1) on the device in FP64
+     * inside every kernel instead of reading the plan's precomputed table. */
+    AMQFT_FLAG_ONTHEFLY_CONSTANTS = 1u,
+    /* Do not consult the tuning table; use the default launch shape. */
+    AMQFT_FLAG_NO_AUTOTUNE = 2u,
+    /* Use the multi-pass (global-memory) path even when a signal fits LDS. */
+    AMQFT_FLAG_FORCE_MULTIPASS = 4u
+};
+
+/* Largest supported log2(N). */
+#define AMQFT_MAX_LOG2N 24
+
+typedef struct amqft_plan_s *amqft_plan;
+
+/* Plan for `batch` signals of length n stored back to back (stride n).
+ * The plan owns the constant table and any workspace; it may be used for
+ * any number of amqft_exec/amqft_exec_adjoint calls but not concurrently on
+ * two streams (workspace is per plan).  batch = 0 is allowed (exec is then
+ * a no-op).  On error *out is set to NULL. */
+amqft_status amqft_plan_create(amqft_plan *out, int64_t n, int64_t batch,
+                               amqft_variant variant, amqft_dtype dtype,
+                               unsigned flags);
+
+/* Plan for `count` signals of (possibly different) power-of-two lengths in
+ * one buffer: signal i has lengths_host[i] points and starts at complex
+ * element offsets_host[i]; offsets_host has count+1 entries, is
+ * non-decreasing, and offsets_host[i+1] - offsets_host[i] >= lengths_host[i]
+ * (signals must not overlap).  Both arrays are host memory and are copied
+ * into the plan.  The plan builds a cost-sorted work list and executes all
+ * signals in one persistent launch. */
+amqft_status amqft_plan_create_many(amqft_plan *out, int64_t count,
+                                    const int64_t *lengths_host,
+                                    const int64_t *offsets_host,
+                                    amqft_variant variant, amqft_dtype dtype,
+                                    unsigned flags);
+
+/* X = F x (eq. qft_0A) for every signal of the plan, asynchronously on
+ * `stream` (a hipStream_t; NULL = the default stream).  in_dev and out_dev
+ * are device pointers to the interleaved complex data in the plan's dtype. */
+amqft_status amqft_exec(amqft_plan plan, const void *in_dev, void *out_dev,
+                        void *stream);
+
+/* y = F^H g, the conjugate transpose (unnormalised): the inverse DFT times N.
+ * Because the DFT matrix is symmetric, F^H g = conj(F conj(g)). */
+amqft_status amqft_exec_adjoint(amqft_plan plan, const void *in_dev,
+                                void *out_dev, void *stream);
+
+/* Fused loss and gradient for loss = sum_b sum_k |w(b,k) * (F x_b)(k)|^2:
+ * reads x (batch, n) and w (batch, n) (both in the plan's dtype), writes
+ * grad_x = 2 F^H(|w|^2 * F x) (same layout) and the per-signal losses
+ * loss_dev[b] (FP32, or FP64 for AMQFT_C128).  grad = dL/dRe + i dL/dIm.
+ * Only plans made by amqft_plan_create; grad_dev may alias x_dev. */
+amqft_status amqft_power_loss_grad(amqft_plan plan, const void *x_dev,
+                                   const void *w_dev, void *grad_dev,
+                                   void *loss_dev, void *stream);
+
+/* Capture the plan's forward (adjoint = 0) or adjoint (adjoint = 1)
+ * execution on the given buffers into a HIP graph owned by the plan, and
+ * launch it on `stream`; later calls with the same buffers replay the graph.
+ * The buffers are part of the graph: passing different pointers re-captures. */
+amqft_status amqft_exec_graph(amqft_plan plan, const void *in_dev,
+                              void *out_dev, int adjoint, void *stream);
+
+/* Free the plan and its device memory.  The caller must have synchronised
+ * every stream the plan ran on.  NULL is accepted. */
+amqft_status amqft_plan_destroy(amqft_plan plan);
+
+/* Bytes of device workspace owned by the plan (0 when none). */
+amqft_status amqft_plan_workspace_size(amqft_plan plan, size_t *bytes);
+
+/* Copy the plan's constant table for length n (n/4 entries, in FP64, as the
+ * kernels read them after rounding to the working precision) into host
+ * memory table_host[0 .. n/4).  Entry p holds f(2 pi p / n) for the
+ * variant's family f in {2cos, 1/(2cos), 2sin, 1/(2sin)} (Sec. 7.1); entry 0
+ * is unused.  For tests of the constant generation. */
+amqft_status amqft_plan_constants(amqft_plan plan, int64_t n, double *table_host,
+                                  int64_t entries);
+
+/* Static description of a status code. */
+const char *amqft_status_string(amqft_status status);
+
+/* Last HIP error string seen by this thread ("" if none). */
+const char *amqft_last_hip_error(void);
+
+/* Library version string. */
+const char *amqft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMQFT_H */

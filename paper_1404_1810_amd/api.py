@@ -1,0 +1,170 @@
+"""PyTorch-facing binding of the AM-QFT library.
+
+Torch supplies device memory and the current HIP stream; every transform step
+runs in the HIP kernels of libamqft.so, reached through the C ABI.
+
+Storage conventions (last dimension = the transform axis):
+  complex128 / complex64 tensors       -> AMQFT_C128 / AMQFT_C64
+  float16 / bfloat16 tensors (..., n, 2) -> AMQFT_C32H / AMQFT_C32B
+                                           (interleaved re/im, FP32 math)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+_DTYPES = {torch.complex128: _lib.C128, torch.complex64: _lib.C64,
+           torch.float16: _lib.C32H, torch.bfloat16: _lib.C32B}
+
+
+def _storage(x: torch.Tensor):
+    """(amqft dtype, n, batch) of a tensor in one of the storage layouts."""
+    if x.dtype not in _DTYPES:
+        raise TypeError("unsupported dtype %s" % x.dtype)
+    dt = _DTYPES[x.dtype]
+    if dt in (_lib.C32H, _lib.C32B):
+        if x.dim() < 2 or x.shape[-1] != 2:
+            raise ValueError("half/bfloat16 storage must have a trailing (re, im) dimension of size 2")
+        n = x.shape[-2]
+        batch = x.numel() // (2 * n) if n else 0
+    else:
+        if x.dim() < 1:
+            raise ValueError("need at least one dimension")
+        n = x.shape[-1]
+        batch = x.numel() // n if n else 0
+    return dt, n, batch
+
+
+def _stream_handle(dev: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+class Plan:
+    """An amqft_plan (constants and workspace live on the device)."""
+
+    def __init__(self, n: int, batch: int, variant: int = 4, dtype: int = _lib.C64, flags: int = 0):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(lib.amqft_plan_create(ctypes.byref(h), int(n), int(batch), int(variant), int(dtype),
+                                         int(flags)), "amqft_plan_create")
+        self._h = h
+        self.n, self.batch, self.variant, self.dtype, self.flags = int(n), int(batch), int(variant), int(dtype), int(flags)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.load().amqft_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            if self._h is not None and self._h.value and torch.cuda.is_available():
+                torch.cuda.synchronize()
+            self.close()
+        except Exception:
+            pass
+
+    def _check_tensor(self, t: torch.Tensor, name: str):
+        if not t.is_cuda:
+            raise ValueError("%s must be a GPU tensor (the AM-QFT path has no CPU fallback)" % name)
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        dt, n, batch = _storage(t)
+        if dt != self.dtype or n != self.n or batch != self.batch:
+            raise ValueError("%s does not match the plan (dtype %d n %d batch %d)" % (name, self.dtype, self.n,
+                                                                                     self.batch))
+
+    def exec(self, x: torch.Tensor, out: torch.Tensor | None = None, adjoint: bool = False) -> torch.Tensor:
+        self._check_tensor(x, "input")
+        y = torch.empty_like(x) if out is None else out
+        self._check_tensor(y, "output")
+        fn = _lib.load().amqft_exec_adjoint if adjoint else _lib.load().amqft_exec
+        _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                      _stream_handle(x.device)), "amqft_exec" + ("_adjoint" if adjoint else ""))
+        return y
+
+    def power_loss_grad(self, x: torch.Tensor, w: torch.Tensor):
+        self._check_tensor(x, "x")
+        self._check_tensor(w, "w")
+        g = torch.empty_like(x)
+        ldt = torch.float64 if self.dtype == _lib.C128 else torch.float32
+        loss = torch.empty(self.batch, dtype=ldt, device=x.device)
+        _lib.check(_lib.load().amqft_power_loss_grad(
+            self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+            ctypes.c_void_p(loss.data_ptr()), _stream_handle(x.device)), "amqft_power_loss_grad")
+        return loss, g
+
+    def constants(self, n: int | None = None):
+        import numpy as np
+        n = self.n if n is None else n
+        out = np.zeros(max(n // 4, 1), dtype=np.float64)
+        _lib.check(_lib.load().amqft_plan_constants(self._h, int(n), ctypes.c_void_p(out.ctypes.data), out.size),
+                   "amqft_plan_constants")
+        return out
+
+
+_plan_cache: dict = {}
+
+
+def get_plan(n: int, batch: int, variant: int, dtype: int, flags: int = 0, device=None) -> Plan:
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    key = (n, batch, variant, dtype, flags, dev)
+    p = _plan_cache.get(key)
+    if p is None:
+        with torch.cuda.device(dev):
+            p = Plan(n, batch, variant, dtype, flags)
+        _plan_cache[key] = p
+    return p
+
+
+def fft(x: torch.Tensor, variant: int = 4, flags: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Unnormalised forward DFT (eq. qft_0A) along the last axis by AM-QFT."""
+    x = x.contiguous()
+    dt, n, batch = _storage(x)
+    return get_plan(n, batch, variant, dt, flags, x.device).exec(x, out=out)
+
+
+def adjoint(g: torch.Tensor, variant: int = 4, flags: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """F^H g (unnormalised inverse DFT) along the last axis."""
+    g = g.contiguous()
+    dt, n, batch = _storage(g)
+    return get_plan(n, batch, variant, dt, flags, g.device).exec(g, out=out, adjoint=True)
+
+
+def ifft(X: torch.Tensor, variant: int = 4) -> torch.Tensor:
+    """Normalised inverse DFT = F^H X / N (the scaling is the caller's step)."""
+    return adjoint(X, variant) / X.shape[-1]
+
+
+class AMQFTFunction(torch.autograd.Function):
+    """y = F x with the hand-written adjoint kernel as its backward:
+    for a real loss L, dL/dx* convention (PyTorch) gives grad_x = F^H grad_y."""
+
+    @staticmethod
+    def forward(ctx, x, variant: int = 4):
+        ctx.variant = variant
+        return fft(x, variant)
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        return adjoint(grad_y.contiguous(), ctx.variant), None
+
+
+def amqft(x: torch.Tensor, variant: int = 4) -> torch.Tensor:
+    """Differentiable AM-QFT forward transform (complex64/complex128)."""
+    return AMQFTFunction.apply(x, variant)
+
+
+def power_loss(x: torch.Tensor, w: torch.Tensor, variant: int = 4):
+    """Fused per-signal loss sum_k |w * F x|^2 and its gradient 2 F^H(|w|^2 F x)
+    in one kernel: returns (loss[batch], grad_x)."""
+    x = x.contiguous()
+    w = w.contiguous()
+    dt, n, batch = _storage(x)
+    return get_plan(n, batch, variant, dt, 0, x.device).power_loss_grad(x, w)

@@ -1,0 +1,109 @@
+// Device-side building blocks of the AM-QFT kernels for gfx950.
+//
+// Complex values are held as (re, im) pairs of the arithmetic type R (float
+// or double); the recursion of the paper has only real coefficients, so the
+// real and imaginary parts of a complex signal run through it in lockstep:
+// the same additions and multiplications per point as the paper's two real
+// passes (Sec. 3.1, decomposition D_c).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace amqft {
+
+template <typename R>
+struct cx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator*(cx<R> a, R k) { return {a.re * k, a.im * k}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cconj(cx<R> a) { return {a.re, -a.im}; }
+
+// cos(pi/4) = sin(pi/4): the single constant of the L = 8 base cases of
+// dct_oo / dst_oo (Sec. 7.1).
+template <typename R> __device__ __forceinline__ R cos_pi_4();
+template <> __device__ __forceinline__ float cos_pi_4<float>() { return 0.70710678118654752440f; }
+template <> __device__ __forceinline__ double cos_pi_4<double>() { return 0.70710678118654752440; }
+
+// ---------------------------------------------------------------------------
+// storage types: interleaved (re, im) pairs
+// ---------------------------------------------------------------------------
+struct bf16x2 {
+    uint16_t re, im;
+};
+
+template <typename S> struct storage;
+
+template <> struct storage<double2> {
+    using R = double;
+    static __device__ __forceinline__ cx<double> ld(const double2* p) { double2 v = *p; return {v.x, v.y}; }
+    static __device__ __forceinline__ void st(double2* p, cx<double> v) { *p = make_double2(v.re, v.im); }
+};
+template <> struct storage<float2> {
+    using R = float;
+    static __device__ __forceinline__ cx<float> ld(const float2* p) { float2 v = *p; return {v.x, v.y}; }
+    static __device__ __forceinline__ void st(float2* p, cx<float> v) { *p = make_float2(v.re, v.im); }
+};
+template <> struct storage<__half2> {
+    using R = float;
+    static __device__ __forceinline__ cx<float> ld(const __half2* p) {
+        float2 v = __half22float2(*p);
+        return {v.x, v.y};
+    }
+    static __device__ __forceinline__ void st(__half2* p, cx<float> v) {
+        *p = __float22half2_rn(make_float2(v.re, v.im));
+    }
+};
+// bfloat16 = the upper 16 bits of an IEEE binary32; stores round to nearest,
+// ties to even; NaN stays NaN.
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+template <> struct storage<bf16x2> {
+    using R = float;
+    static __device__ __forceinline__ cx<float> ld(const bf16x2* p) {
+        bf16x2 v = *p;
+        return {bf16_to_f32(v.re), bf16_to_f32(v.im)};
+    }
+    static __device__ __forceinline__ void st(bf16x2* p, cx<float> v) {
+        bf16x2 o;
+        o.re = f32_to_bf16(v.re);
+        o.im = f32_to_bf16(v.im);
+        *p = o;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// variant traits (Sec. 6 and the general notes at its end)
+// ---------------------------------------------------------------------------
+template <int V>
+struct variant_traits {
+    // skeleton A (time indices split first: dct_ot/dst_ot) or B (harmonics
+    // first: dct_to/dst_to)
+    static constexpr bool skel_a = (V == 1 || V == 4 || V == 5 || V == 8);
+    // M5..M8 turn a DCT mother into a DST child and vice versa
+    static constexpr bool switches = V >= 5;
+    // M1, M3, M5, M7 contain a sequential recurrence (with one halving)
+    static constexpr bool recurrence = (V == 1 || V == 3 || V == 5 || V == 7);
+    // coefficient of the previous term in that recurrence
+    static constexpr int sign = (V == 1 || V == 3) ? -1 : 1;
+};
+
+// Constant-table family per variant (Sec. 7.1): 0 = 2cos, 1 = 1/(2cos),
+// 2 = 2sin, 3 = 1/(2sin).
+__host__ __device__ constexpr int const_family(int v) {
+    return (v == 1 || v == 3) ? 0 : (v == 2 || v == 4) ? 1 : (v == 5 || v == 7) ? 2 : 3;
+}
+
+}  // namespace amqft

@@ -1,0 +1,35 @@
+// Host-side interface between the C ABI (amqft_api.cpp) and the kernel
+// launchers (amqft_lds.hip, ...).  Not installed; not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace amqft {
+
+// Largest log2(N) a single workgroup keeps resident in LDS, per arithmetic
+// precision (FP32 compute: 2^14 points = 128 KiB; FP64: 2^13).
+constexpr int kMaxLdsLog2F32 = 14;
+constexpr int kMaxLdsLog2F64 = 13;
+
+struct lds_launch {
+    int variant;       // 1..8
+    int dtype;         // amqft_dtype
+    int logn;          // log2 N, 0..kMaxLds*
+    int64_t batch;     // signals (stride N)
+    const void* in;    // device
+    void* out;         // device
+    const void* ktab;  // device constant table (R values), entries (1<<ktab_log2n)/4
+    int ktab_log2n;    // log2 of the length the table was built for
+    int conj_in;       // conjugate the input on load
+    int conj_out;      // conjugate the output on store
+    int onthefly;      // generate constants on the device (FP64) instead
+};
+
+// Launch the LDS-resident engine; returns the hipError_t of the launch.
+hipError_t launch_lds(const lds_launch& a, hipStream_t stream);
+
+// Bytes of dynamic LDS and threads per workgroup the LDS engine uses.
+void lds_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
+
+}  // namespace amqft

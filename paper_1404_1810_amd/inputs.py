@@ -19,9 +19,12 @@ SEEDS = {"fp64_n256": 0, "fp32_n4096": 0, "uneven_lengths": 2, "uneven_entries":
          "grad_x": 0, "grad_w": 1, "fp16_n2p20": 0}
 
 
-def _rows(seed: int, batch: int, n: int, kind: str, start: int = 0) -> np.ndarray:
-    """complex128 array (batch, n); rows start..start+batch-1 of the stream."""
-    out = np.empty((batch, n), dtype=np.complex128)
+def _rows(seed: int, batch: int, n: int, kind: str, start: int = 0, out: np.ndarray | None = None) -> np.ndarray:
+    """complex128 array (batch, n); rows start..start+batch-1 of the stream
+    (written into ``out`` when given, which avoids fresh page faults)."""
+    if out is None:
+        out = np.empty((batch, n), dtype=np.complex128)
+    parts = out.view(np.float64).reshape(batch, n, 2)  # (re, im) interleaved
     for b in range(batch):
         g = np.random.default_rng([seed, start + b])
         if kind == "normal":
@@ -32,14 +35,14 @@ def _rows(seed: int, batch: int, n: int, kind: str, start: int = 0) -> np.ndarra
             im = g.random(n) * 2.0 - 1.0
         else:
             raise ValueError(kind)
-        out[b].real = re
-        out[b].imag = im
+        parts[b, :, 0] = re
+        parts[b, :, 1] = im
     return out
 
 
-def complex_normal(seed: int, batch: int, n: int, start: int = 0) -> np.ndarray:
+def complex_normal(seed: int, batch: int, n: int, start: int = 0, out: np.ndarray | None = None) -> np.ndarray:
     """Re and Im i.i.d. N(0,1), generated in float64 (cast by the caller)."""
-    return _rows(seed, batch, n, "normal", start)
+    return _rows(seed, batch, n, "normal", start, out)
 
 
 def complex_uniform(seed: int, batch: int, n: int, start: int = 0) -> np.ndarray:
@@ -50,6 +53,15 @@ def complex_uniform(seed: int, batch: int, n: int, start: int = 0) -> np.ndarray
 def cfg_fp64_n256(batch: int = 64, n: int = 256) -> np.ndarray:
     """Configuration 1: complex128, 64 x N=256, U[-1,1), seed 0."""
     return complex_uniform(SEEDS["fp64_n256"], batch, n)
+
+
+def chunks(kind: str, seed: int, batch: int, n: int, chunk: int = 512):
+    """Yield (start, rows) of a large batch, chunk rows at a time, reusing one
+    complex128 buffer (the caller copies each chunk out before the next)."""
+    buf = np.empty((min(chunk, max(batch, 1)), n), dtype=np.complex128)
+    for s0 in range(0, batch, chunk):
+        m = min(chunk, batch - s0)
+        yield s0, _rows(seed, m, n, kind, s0, buf[:m])
 
 
 def cfg_fp32_n4096(batch: int = 16384, n: int = 4096, start: int = 0) -> np.ndarray:

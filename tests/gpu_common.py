@@ -1,0 +1,42 @@
+"""Shared helpers of the GPU tests: tolerances and oracle references.
+
+Tolerance rule (relative L2 error against the FP64 oracle run on the same
+stored input):
+  * variants 1-4: 1e-12 (FP64 arithmetic) and 1e-5 (FP32 arithmetic) at every
+    size -- the accuracy targets of this project;
+  * variants 5-8 are ill-conditioned by construction (Sec. 7.3: their error
+    "grows far faster"); where their own FP64/FP32 error is above those
+    targets the bound is 20x the error of the oracle's same-variant,
+    same-precision emulation (plus a floor), i.e. the GPU must be as accurate
+    as a faithful implementation of the same variant can be.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    n = np.linalg.norm(b.ravel())
+    d = np.linalg.norm((a - b).ravel())
+    return d / n if n > 0 else d
+
+
+def truth(x: np.ndarray, variant: int = 4) -> np.ndarray:
+    """FP64 oracle of the given variant on the (already quantised) input."""
+    return oracle.cdft(np.asarray(x, dtype=np.complex128), variant, prec="f64")
+
+
+def bound(variant: int, f64: bool, x: np.ndarray, ref: np.ndarray) -> float:
+    base = 1e-12 if f64 else 1e-5
+    if variant <= 4:
+        return base
+    emu = oracle.cdft(np.asarray(x, dtype=np.complex128 if f64 else np.complex64), variant,
+                      prec="f64" if f64 else "f32")
+    e = rel(emu, ref)
+    if not np.isfinite(e):
+        return np.inf
+    return max(base, 20.0 * e)

@@ -1,0 +1,96 @@
+"""The C ABI: the library loads, exports every function include/amqft.h
+declares, and rejects invalid arguments with the documented status codes
+before making any HIP call (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1404_1810_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "amqft.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(amqft_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1404_1810_amd.build import build
+        build(verbose=False)
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings(lib):
+    for s in range(6):
+        assert lib.amqft_status_string(s)
+    assert b"gfx950" in lib.amqft_version()
+
+
+def _create(lib, n, batch=1, variant=4, dtype=1, flags=0, null_out=False):
+    h = ctypes.c_void_p(12345)
+    rc = lib.amqft_plan_create(None if null_out else ctypes.byref(h), n, batch, variant, dtype, flags)
+    return rc, h
+
+
+@pytest.mark.parametrize("n", [0, -4, 3, 6, 12, 1000, 4097])
+def test_not_pow2(lib, n):
+    rc, h = _create(lib, n)
+    assert rc == _lib.ERR_NOT_POW2
+    assert not h.value
+
+
+@pytest.mark.parametrize("kw", [dict(variant=0), dict(variant=9), dict(dtype=7), dict(dtype=-1),
+                                dict(batch=-1), dict(flags=64), dict(null_out=True)])
+def test_invalid_args(lib, kw):
+    rc, _ = _create(lib, 64, **kw)
+    assert rc == _lib.ERR_INVALID_ARG
+
+
+def test_too_large(lib):
+    rc, _ = _create(lib, 1 << 30)
+    assert rc == _lib.ERR_UNSUPPORTED
+
+
+def test_null_plan_calls(lib):
+    assert lib.amqft_exec(None, None, None, None) == _lib.ERR_INVALID_ARG
+    assert lib.amqft_exec_adjoint(None, None, None, None) == _lib.ERR_INVALID_ARG
+    assert lib.amqft_power_loss_grad(None, None, None, None, None, None) == _lib.ERR_INVALID_ARG
+    assert lib.amqft_exec_graph(None, None, None, 0, None) == _lib.ERR_INVALID_ARG
+    assert lib.amqft_plan_destroy(None) == _lib.OK
+    sz = ctypes.c_size_t(7)
+    assert lib.amqft_plan_workspace_size(None, ctypes.byref(sz)) == _lib.ERR_INVALID_ARG
+    assert lib.amqft_plan_constants(None, 64, None, 0) == _lib.ERR_INVALID_ARG
+
+
+def test_create_many_validation(lib):
+    import numpy as np
+    h = ctypes.c_void_p()
+    L = np.array([16, 32, 48], dtype=np.int64)
+    O = np.array([0, 16, 48, 96], dtype=np.int64)
+    rc = lib.amqft_plan_create_many(ctypes.byref(h), 3, L.ctypes.data, O.ctypes.data, 4, 1, 0)
+    assert rc == _lib.ERR_NOT_POW2
+    L = np.array([16, 32, 64], dtype=np.int64)
+    O = np.array([0, 16, 40, 104], dtype=np.int64)  # second signal overlaps the third
+    rc = lib.amqft_plan_create_many(ctypes.byref(h), 3, L.ctypes.data, O.ctypes.data, 4, 1, 0)
+    assert rc == _lib.ERR_INVALID_ARG
+    O = np.array([0, 16, 48, 112], dtype=np.int64)
+    rc = lib.amqft_plan_create_many(ctypes.byref(h), 3, L.ctypes.data, O.ctypes.data, 0, 1, 0)
+    assert rc == _lib.ERR_INVALID_ARG
+    rc = lib.amqft_plan_create_many(ctypes.byref(h), -1, L.ctypes.data, O.ctypes.data, 4, 1, 0)
+    assert rc == _lib.ERR_INVALID_ARG
+    rc = lib.amqft_plan_create_many(ctypes.byref(h), 3, None, O.ctypes.data, 4, 1, 0)
+    assert rc == _lib.ERR_INVALID_ARG

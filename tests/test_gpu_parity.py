@@ -1,0 +1,122 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every case prints its identity before it touches the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import bound, rel, truth
+from paper_1404_1810_amd import inputs
+
+torch = pytest.importorskip("torch")
+
+VARIANTS = list(range(1, 9))
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def _api():
+    from paper_1404_1810_amd import api
+    return api
+
+
+def _run(x_np, variant, dtype, flags=0, adjoint=False):
+    api = _api()
+    if dtype == "c128":
+        x = torch.from_numpy(np.ascontiguousarray(x_np, dtype=np.complex128)).cuda()
+    else:
+        x = torch.from_numpy(np.ascontiguousarray(x_np, dtype=np.complex64)).cuda()
+    f = api.adjoint if adjoint else api.fft
+    y = f(x, variant, flags=flags)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+SIZES_F32 = [1, 2, 4, 8, 16, 32, 64, 128, 256, 1024, 4096, 16384]
+SIZES_F64 = [1, 2, 4, 8, 16, 64, 256, 1024, 8192]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_parity_fp32(variant):
+    for n in SIZES_F32:
+        batch = 3 if n >= 4096 else 37  # ragged: not a multiple of signals-per-workgroup
+        _say("fp32 parity variant", variant, "n", n, "batch", batch)
+        x = inputs.complex_normal(1000 + n, batch, n).astype(np.complex64)
+        ref = truth(x, 2 if variant in (2, 3, 6, 7) else 4)
+        y = _run(x, variant, "c64")
+        assert y.dtype == np.complex64
+        b = bound(variant, False, x, ref)
+        e = rel(y, ref)
+        assert e <= b, (variant, n, e, b)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_parity_fp64(variant):
+    for n in SIZES_F64:
+        batch = 2 if n >= 4096 else 19
+        _say("fp64 parity variant", variant, "n", n, "batch", batch)
+        x = inputs.complex_uniform(2000 + n, batch, n)
+        ref = truth(x, 4)
+        y = _run(x, variant, "c128")
+        b = bound(variant, True, x, ref)
+        e = rel(y, ref)
+        assert e <= b, (variant, n, e, b)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_adjoint_parity(variant):
+    n, batch = 512, 9
+    _say("adjoint variant", variant)
+    g = inputs.complex_normal(77, batch, n)
+    ref = np.conj(truth(np.conj(g), 4))  # F^H g
+    y = _run(g, variant, "c128", adjoint=True)
+    assert rel(y, ref) <= bound(variant, True, np.conj(g), np.conj(ref))
+
+
+@pytest.mark.gpu
+def test_onthefly_constants_match_table():
+    n, batch = 1024, 5
+    x = inputs.complex_normal(5, batch, n).astype(np.complex64)
+    for v in VARIANTS:
+        _say("on-the-fly constants variant", v)
+        a = _run(x, v, "c64", flags=0)
+        b = _run(x, v, "c64", flags=1)
+        # the FP64 device constants round to the same FP32 table entries
+        # except for rare double-rounding ties, so the results agree closely
+        assert rel(b, a) < 1e-6, v
+
+
+@pytest.mark.gpu
+def test_in_place_and_empty():
+    api = _api()
+    n = 256
+    x_np = inputs.complex_normal(9, 7, n).astype(np.complex64)
+    x = torch.from_numpy(x_np).cuda()
+    _say("in-place n", n)
+    y = api.fft(x.clone(), 4)
+    z = x.clone()
+    api.fft(z, 4, out=z)
+    torch.cuda.synchronize()
+    assert torch.equal(y, z)
+    _say("empty batch")
+    e = torch.empty((0, n), dtype=torch.complex64, device="cuda")
+    assert api.fft(e, 4).shape == (0, n)
+
+
+@pytest.mark.gpu
+def test_deterministic():
+    api = _api()
+    x = torch.from_numpy(inputs.complex_normal(3, 64, 4096).astype(np.complex64)).cuda()
+    for v in (1, 4, 7):
+        _say("determinism variant", v)
+        a = api.fft(x, v)
+        b = api.fft(x, v)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
