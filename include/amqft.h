@@ -116,7 +116,8 @@ amqft_status amqft_exec_adjoint(amqft_plan plan, const void *in_dev,
  * reads x (batch, n) and w (batch, n) (both in the plan's dtype), writes
  * grad_x = 2 F^H(|w|^2 * F x) (same layout) and the per-signal losses
  * loss_dev[b] (FP32, or FP64 for AMQFT_C128).  grad = dL/dRe + i dL/dIm.
- * Only plans made by amqft_plan_create; grad_dev may alias x_dev. */
+ * Only plans made by amqft_plan_create with n >= 4 (AMQFT_ERR_UNSUPPORTED
+ * otherwise); grad_dev may alias x_dev but not w_dev. */
 amqft_status amqft_power_loss_grad(amqft_plan plan, const void *x_dev,
                                    const void *w_dev, void *grad_dev,
                                    void *loss_dev, void *stream);

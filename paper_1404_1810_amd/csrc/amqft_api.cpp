@@ -193,9 +193,24 @@ amqft_status amqft_exec_adjoint(amqft_plan p, const void* in, void* out, void* s
 
 amqft_status amqft_power_loss_grad(amqft_plan p, const void* x, const void* w, void* grad, void* loss,
                                    void* stream) {
-    if (!p || !x || !w || !grad || !loss) return AMQFT_ERR_INVALID_ARG;
-    (void)stream;
-    return AMQFT_ERR_UNSUPPORTED;
+    if (!p) return AMQFT_ERR_INVALID_ARG;
+    if (p->batch == 0) return AMQFT_OK;
+    if (!x || !w || !grad || !loss) return AMQFT_ERR_INVALID_ARG;
+    if (p->logn < 2) return AMQFT_ERR_UNSUPPORTED;
+    loss_launch a{};
+    a.variant = p->variant;
+    a.dtype = p->dtype;
+    a.logn = p->logn;
+    a.batch = p->batch;
+    a.x = x;
+    a.w = w;
+    a.grad = grad;
+    a.loss = loss;
+    a.ktab = p->ktab;
+    a.ktab_log2n = p->ktab_log2n;
+    a.onthefly = (p->flags & AMQFT_FLAG_ONTHEFLY_CONSTANTS) != 0;
+    hipError_t e = launch_loss(a, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? AMQFT_OK : hip_fail(e);
 }
 
 amqft_status amqft_exec_graph(amqft_plan p, const void* in, void* out, int adjoint, void* stream) {

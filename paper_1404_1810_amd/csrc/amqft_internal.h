@@ -26,6 +26,21 @@ struct lds_launch {
     int onthefly;      // generate constants on the device (FP64) instead
 };
 
+struct loss_launch {
+    int variant, dtype, logn;  // logn >= 2
+    int64_t batch;
+    const void* x;     // device, (batch, N) storage type
+    const void* w;     // device, (batch, N) storage type
+    void* grad;        // device, (batch, N) storage type
+    void* loss;        // device, batch values of the arithmetic type
+    const void* ktab;
+    int ktab_log2n;
+    int onthefly;
+};
+
+// Fused loss/gradient kernel (forward, |w|^2 weighting, adjoint).
+hipError_t launch_loss(const loss_launch& a, hipStream_t stream);
+
 // Launch the LDS-resident engine; returns the hipError_t of the launch.
 hipError_t launch_lds(const lds_launch& a, hipStream_t stream);
 

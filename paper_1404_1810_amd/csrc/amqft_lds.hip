@@ -702,6 +702,28 @@ __device__ void load_constants(R* kt, const R* ktab, int Q, int kshift, bool ont
     }
 }
 
+// the recursion of both sides between the D_r split and the D_c combine
+template <int V, typename R>
+__device__ void core(cx<R>* w, const R* kt, cx<R>* scr, int ltid, int T, int D, int H) {
+    using VT = variant_traits<V>;
+    if constexpr (VT::skel_a) {
+        for (int l = 0; l < D; ++l) a_fwd_level<V, R>(w, kt, ltid, T, D, H, l);
+        for (int l = D - 1; l >= 0; --l) {
+            if constexpr (VT::recurrence) a_bwd_scan_level<V, R>(w, scr, ltid, T, D, H, l);
+            else a_bwd_level<V, R>(w, ltid, T, D, H, l);
+        }
+        a_chain<R>(w, ltid, T, D, H);
+    } else {
+        b_chain_fwd<R>(w, ltid, T, D, H);
+        for (int l = 0; l < D; ++l) {
+            if constexpr (VT::recurrence) b_fwd_scan_level<V, R>(w, scr, ltid, T, D, H, l);
+            else b_fwd_level<V, R>(w, ltid, T, D, H, l);
+        }
+        for (int l = D - 1; l >= 0; --l) b_bwd_level<V, R>(w, kt, ltid, T, D, H, l);
+        b_chain_bwd<R>(w, ltid, T, D, H);
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -735,23 +757,107 @@ __global__ __launch_bounds__(1024) void amqft_lds_kernel(const S* __restrict__ i
     load_constants<V, R>(kt, ktab, Q, kshift, onthefly, logn);
     load_signal<VT::skel_a, S, R>(w, x, ltid, T, D, H, conj_in, valid);
     __syncthreads();
-    if constexpr (VT::skel_a) {
-        for (int l = 0; l < D; ++l) a_fwd_level<V, R>(w, kt, ltid, T, D, H, l);
-        for (int l = D - 1; l >= 0; --l) {
-            if constexpr (VT::recurrence) a_bwd_scan_level<V, R>(w, scr, ltid, T, D, H, l);
-            else a_bwd_level<V, R>(w, ltid, T, D, H, l);
-        }
-        a_chain<R>(w, ltid, T, D, H);
-    } else {
-        b_chain_fwd<R>(w, ltid, T, D, H);
-        for (int l = 0; l < D; ++l) {
-            if constexpr (VT::recurrence) b_fwd_scan_level<V, R>(w, scr, ltid, T, D, H, l);
-            else b_fwd_level<V, R>(w, ltid, T, D, H, l);
-        }
-        for (int l = D - 1; l >= 0; --l) b_bwd_level<V, R>(w, kt, ltid, T, D, H, l);
-        b_chain_bwd<R>(w, ltid, T, D, H);
-    }
+    core<V, R>(w, kt, scr, ltid, T, D, H);
     store_signal<S, R>(w, y, ltid, T, H, conj_out, valid);
+}
+
+// ---------------------------------------------------------------------------
+// fused loss and gradient, loss_b = sum_k |w(k) (F x_b)(k)|^2,
+// grad_b = 2 F^H(|w|^2 F x_b) = conj(F conj(2 |w|^2 F x_b)):
+// forward recursion, then the D_c combine of the forward fused with the
+// weighting and the D_r split of the adjoint, the recursion again, and the
+// final D_c combine with conjugation on store.
+// ---------------------------------------------------------------------------
+template <int V, typename S>
+__global__ __launch_bounds__(1024) void amqft_loss_kernel(const S* __restrict__ xin, const S* __restrict__ win,
+                                                           S* __restrict__ grad,
+                                                           typename storage<S>::R* __restrict__ loss,
+                                                           const typename storage<S>::R* __restrict__ ktab,
+                                                           int logn, long long batch, int kshift, int flags) {
+    using R = typename storage<S>::R;
+    using VT = variant_traits<V>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const bool onthefly = flags & 4;
+    const int N = 1 << logn;
+    const int H = N >> 1;
+    const int D = logn - 2;
+    const int Q = 1 << D;
+    const int T = (N >> 4) > 1 ? (N >> 4) : 1;
+    const int spw = blockDim.x / T;
+    const int slot = threadIdx.x / T;
+    const int ltid = threadIdx.x - slot * T;
+    const long long sig = (long long)blockIdx.x * spw + slot;
+    const bool valid = sig < batch;
+    R* kt = reinterpret_cast<R*>(smem);
+    const size_t kt_bytes = ((size_t)Q * sizeof(R) + 15) & ~(size_t)15;
+    cx<R>* w = reinterpret_cast<cx<R>*>(smem + kt_bytes) + (size_t)slot * (N + T);
+    cx<R>* scr = w + N;
+    const S* x = xin + (valid ? sig : 0) * (long long)N;
+    const S* wt = win + (valid ? sig : 0) * (long long)N;
+    S* g = grad + (valid ? sig : 0) * (long long)N;
+
+    load_constants<V, R>(kt, ktab, Q, kshift, onthefly, logn);
+    load_signal<VT::skel_a, S, R>(w, x, ltid, T, D, H, false, valid);
+    __syncthreads();
+    core<V, R>(w, kt, scr, ltid, T, D, H);
+    // combine + weight + split for the adjoint (conj of the weighted spectrum)
+    R part = R(0);
+    cx<R> a[KMAX], b[KMAX];
+    int kk[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int kidx0 = ltid + k * T;
+        kk[k] = kidx0;
+        if (kidx0 < H && valid) {
+            cx<R> y0, y1;
+            if (kidx0 == 0) {
+                y0 = w[0];
+                y1 = w[H];
+            } else {
+                const cx<R> C = w[kidx0], Dd = w[H + kidx0];
+                y0 = {C.re + Dd.im, C.im - Dd.re};  // Y(k)
+                y1 = {C.re - Dd.im, C.im + Dd.re};  // Y(N-k)
+            }
+            const cx<R> w0 = storage<S>::ld(wt + kidx0);
+            const cx<R> w1 = storage<S>::ld(wt + (kidx0 == 0 ? H : N - kidx0));
+            const R m0 = w0.re * w0.re + w0.im * w0.im;
+            const R m1 = w1.re * w1.re + w1.im * w1.im;
+            part += m0 * (y0.re * y0.re + y0.im * y0.im) + m1 * (y1.re * y1.re + y1.im * y1.im);
+            a[k] = cconj(y0 * (R(2) * m0));  // conj of g(k)
+            b[k] = cconj(y1 * (R(2) * m1));  // conj of g(N-k)
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        const int m = kk[k];
+        if (m < H && valid) {
+            if (m == 0) {
+                w[0] = a[k];
+                w[H] = b[k];
+            } else {
+                int pos = m;
+                if (VT::skel_a) {
+                    const int j = __ffs(m) - 1;
+                    pos = (1 << (D - j)) + (m >> (j + 1));
+                }
+                w[pos] = a[k] + b[k];
+                w[H + pos] = a[k] - b[k];
+            }
+        }
+    }
+    // per-signal loss: reduce the partial sums of the T threads of the signal
+    cx<R>* red = scr;
+    red[ltid] = {part, R(0)};
+    __syncthreads();
+    if (ltid == 0 && valid) {
+        R s = R(0);
+        for (int u = 0; u < T; ++u) s += red[u].re;
+        loss[sig] = s;
+    }
+    __syncthreads();
+    core<V, R>(w, kt, scr, ltid, T, D, H);
+    store_signal<S, R>(w, g, ltid, T, H, true, valid);
 }
 
 // N = 1 (identity) and N = 2 (direct definition of the CDFT, Sec. 4)
@@ -816,6 +922,52 @@ static hipError_t launch_typed(const lds_launch& a, hipStream_t stream) {
                        static_cast<const S*>(a.in), static_cast<S*>(a.out), static_cast<const R*>(a.ktab), a.logn,
                        (long long)a.batch, kshift, flags);
     return hipGetLastError();
+}
+
+template <int V, typename S>
+static hipError_t launch_loss_typed(const loss_launch& a, hipStream_t stream) {
+    using R = typename storage<S>::R;
+    if (a.batch <= 0) return hipSuccess;
+    int threads, spw;
+    size_t lds;
+    lds_shape(a.logn, a.dtype, &threads, &spw, &lds);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_loss_kernel<V, S>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const long long grid = (a.batch + spw - 1) / spw;
+    const int kshift = a.ktab_log2n - a.logn;
+    hipLaunchKernelGGL((amqft_loss_kernel<V, S>), dim3((unsigned)grid), dim3(threads), lds, stream,
+                       static_cast<const S*>(a.x), static_cast<const S*>(a.w), static_cast<S*>(a.grad),
+                       static_cast<R*>(a.loss), static_cast<const R*>(a.ktab), a.logn, (long long)a.batch, kshift,
+                       a.onthefly ? 4 : 0);
+    return hipGetLastError();
+}
+
+template <int V>
+static hipError_t launch_loss_v(const loss_launch& a, hipStream_t s) {
+    switch (a.dtype) {
+    case 0: return launch_loss_typed<V, double2>(a, s);
+    case 1: return launch_loss_typed<V, float2>(a, s);
+    case 2: return launch_loss_typed<V, __half2>(a, s);
+    default: return launch_loss_typed<V, bf16x2>(a, s);
+    }
+}
+
+hipError_t launch_loss(const loss_launch& a, hipStream_t s) {
+    switch (a.variant) {
+    case 1: return launch_loss_v<1>(a, s);
+    case 2: return launch_loss_v<2>(a, s);
+    case 3: return launch_loss_v<3>(a, s);
+    case 4: return launch_loss_v<4>(a, s);
+    case 5: return launch_loss_v<5>(a, s);
+    case 6: return launch_loss_v<6>(a, s);
+    case 7: return launch_loss_v<7>(a, s);
+    default: return launch_loss_v<8>(a, s);
+    }
 }
 
 template <int V>

@@ -1,0 +1,68 @@
+"""FP16 / BF16 storage with FP32 arithmetic (LDS-resident sizes).
+
+Reference: the FP64 oracle run on the same stored (quantised) input.  The
+error then comes from FP32 arithmetic plus the rounding of the output to the
+storage type; bounds 5e-4 (FP16) and 4e-3 (BF16, 8x the unit roundoff of FP16)
+for variants 1-4.  Variants 5-8 are reported, not bounded, beyond the sizes
+where FP32 keeps them accurate.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import rel, truth
+from paper_1404_1810_amd import inputs
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def _half_pairs(z):
+    out = np.empty(z.shape + (2,), dtype=np.float16)
+    out[..., 0] = z.real
+    out[..., 1] = z.imag
+    return out
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_fp16_storage(variant):
+    from paper_1404_1810_amd import api
+    for n in (64, 1024, 16384):
+        batch = 3
+        _say("fp16 variant", variant, "n", n)
+        h = _half_pairs(inputs.complex_uniform(40 + n, batch, n))
+        xq = h[..., 0].astype(np.float64) + 1j * h[..., 1].astype(np.float64)
+        y = api.fft(torch.from_numpy(h).cuda(), variant).cpu().numpy()
+        yc = y[..., 0].astype(np.float64) + 1j * y[..., 1].astype(np.float64)
+        e = rel(yc, truth(xq))
+        _say("  rel err", e)
+        if variant <= 4:
+            assert e < 5e-4, (variant, n, e)
+        elif n <= 64:
+            assert e < 5e-4, (variant, n, e)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", [2, 4])
+def test_bf16_storage(variant):
+    from paper_1404_1810_amd import api
+    for n in (64, 4096):
+        batch = 3
+        _say("bf16 variant", variant, "n", n)
+        z = inputs.complex_uniform(50 + n, batch, n)
+        pairs = np.stack([z.real, z.imag], axis=-1)
+        bits = inputs.to_bf16_bits(pairs)
+        xq64 = inputs.from_bf16_bits(bits).astype(np.float64)
+        xq = xq64[..., 0] + 1j * xq64[..., 1]
+        xt = torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
+        y = api.fft(xt, variant)
+        yb = y.view(torch.int16).cpu().numpy().view(np.uint16)
+        yf = inputs.from_bf16_bits(yb).astype(np.float64)
+        e = rel(yf[..., 0] + 1j * yf[..., 1], truth(xq))
+        _say("  rel err", e)
+        assert e < 4e-3, (variant, n, e)
