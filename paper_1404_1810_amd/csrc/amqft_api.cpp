@@ -30,6 +30,12 @@ struct amqft_plan_s {
     int ktab_log2n = 2;
     std::vector<double> ktab_host;  // FP64 values as rounded to working precision
     int device = 0;
+    // multi-pass (signals larger than LDS)
+    bool multipass = false;
+    int sb = 0;
+    int64_t chunk = 0;
+    void* ws[3] = {nullptr, nullptr, nullptr};
+    size_t ws_bytes = 0;
 };
 
 namespace {
@@ -99,6 +105,27 @@ amqft_status exec_common(amqft_plan p, const void* in, void* out, void* stream, 
     if (!p) return AMQFT_ERR_INVALID_ARG;
     if (p->batch == 0) return AMQFT_OK;  // nothing to read or write; pointers may be NULL
     if (!in || !out) return AMQFT_ERR_INVALID_ARG;
+    if (p->multipass) {
+        mp_launch m{};
+        m.variant = p->variant;
+        m.dtype = p->dtype;
+        m.logn = p->logn;
+        m.sb = p->sb;
+        m.batch = p->batch;
+        m.chunk = p->chunk;
+        m.in = in;
+        m.out = out;
+        m.ws0 = p->ws[0];
+        m.ws1 = p->ws[1];
+        m.ws2 = p->ws[2];
+        m.ktab = p->ktab;
+        m.ktab_log2n = p->ktab_log2n;
+        m.conj_in = adjoint;
+        m.conj_out = adjoint;
+        m.onthefly = (p->flags & AMQFT_FLAG_ONTHEFLY_CONSTANTS) != 0;
+        hipError_t e = launch_multipass(m, static_cast<hipStream_t>(stream));
+        return e == hipSuccess ? AMQFT_OK : hip_fail(e);
+    }
     lds_launch a{};
     a.variant = p->variant;
     a.dtype = p->dtype;
@@ -145,7 +172,8 @@ amqft_status amqft_plan_create(amqft_plan* out, int64_t n, int64_t batch, amqft_
     const int logn = log2_exact(n);
     if (logn < 0) return AMQFT_ERR_NOT_POW2;
     if (logn > AMQFT_MAX_LOG2N) return AMQFT_ERR_UNSUPPORTED;
-    if (logn > max_lds_log2((int)dtype) || (flags & AMQFT_FLAG_FORCE_MULTIPASS)) return AMQFT_ERR_UNSUPPORTED;
+    const bool mp = logn > max_lds_log2((int)dtype) || (flags & AMQFT_FLAG_FORCE_MULTIPASS);
+    if (mp && logn < 5) return AMQFT_ERR_UNSUPPORTED;  // multi-pass needs a block of at least 8 points
     if (batch > (int64_t(1) << 40)) return AMQFT_ERR_UNSUPPORTED;
     amqft_plan_s* p = new (std::nothrow) amqft_plan_s();
     if (!p) return AMQFT_ERR_ALLOC;
@@ -159,6 +187,20 @@ amqft_status amqft_plan_create(amqft_plan* out, int64_t n, int64_t batch, amqft_
     if (e != hipSuccess) { delete p; return hip_fail(e); }
     amqft_status st = build_constants(p, logn);
     if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
+    if (mp) {
+        p->multipass = true;
+        // forced (test) plans use small sub-blocks so that several global levels run
+        p->sb = (flags & AMQFT_FLAG_FORCE_MULTIPASS) ? std::max(2, std::min(multipass_sb((int)dtype), logn - 5))
+                                                     : std::min(multipass_sb((int)dtype), logn - 3);
+        const size_t per = multipass_ws_bytes_per_signal(logn, (int)dtype);
+        const size_t cap = size_t(1) << 30;  // bytes per workspace buffer
+        p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per)));
+        p->ws_bytes = 3 * (size_t)p->chunk * per;
+        for (int i = 0; i < 3 && batch > 0; ++i) {
+            hipError_t e = hipMalloc(&p->ws[i], (size_t)p->chunk * per);
+            if (e != hipSuccess) { p->ws[i] = nullptr; amqft_plan_destroy(p); return hip_fail(e); }
+        }
+    }
     *out = p;
     return AMQFT_OK;
 }
@@ -196,7 +238,7 @@ amqft_status amqft_power_loss_grad(amqft_plan p, const void* x, const void* w, v
     if (!p) return AMQFT_ERR_INVALID_ARG;
     if (p->batch == 0) return AMQFT_OK;
     if (!x || !w || !grad || !loss) return AMQFT_ERR_INVALID_ARG;
-    if (p->logn < 2) return AMQFT_ERR_UNSUPPORTED;
+    if (p->logn < 2 || p->multipass) return AMQFT_ERR_UNSUPPORTED;
     loss_launch a{};
     a.variant = p->variant;
     a.dtype = p->dtype;
@@ -222,13 +264,15 @@ amqft_status amqft_exec_graph(amqft_plan p, const void* in, void* out, int adjoi
 amqft_status amqft_plan_destroy(amqft_plan p) {
     if (!p) return AMQFT_OK;
     if (p->ktab) (void)hipFree(p->ktab);
+    for (void* w : p->ws)
+        if (w) (void)hipFree(w);
     delete p;
     return AMQFT_OK;
 }
 
 amqft_status amqft_plan_workspace_size(amqft_plan p, size_t* bytes) {
     if (!p || !bytes) return AMQFT_ERR_INVALID_ARG;
-    *bytes = 0;
+    *bytes = p->ws_bytes;
     return AMQFT_OK;
 }
 

@@ -44,6 +44,27 @@ hipError_t launch_loss(const loss_launch& a, hipStream_t stream);
 // Launch the LDS-resident engine; returns the hipError_t of the launch.
 hipError_t launch_lds(const lds_launch& a, hipStream_t stream);
 
+// Multi-pass engine for signals larger than LDS (amqft_multipass.hip).
+struct mp_launch {
+    int variant, dtype, logn;
+    int sb;             // log2 of the sub-block size finished in LDS (2..12)
+    int64_t batch;
+    int64_t chunk;      // signals per round (workspace capacity)
+    const void* in;
+    void* out;
+    void* ws0;          // workspaces: chunk * N complex values of the
+    void* ws1;          // arithmetic type each
+    void* ws2;
+    const void* ktab;
+    int ktab_log2n;
+    int conj_in, conj_out, onthefly;
+};
+hipError_t launch_multipass(const mp_launch& m, hipStream_t stream);
+// default sub-block exponent for a storage type (largest the LDS engine holds)
+int multipass_sb(int dtype);
+// bytes of one workspace buffer per signal
+size_t multipass_ws_bytes_per_signal(int logn, int dtype);
+
 // Bytes of dynamic LDS and threads per workgroup the LDS engine uses.
 void lds_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
 

@@ -120,3 +120,37 @@ def test_deterministic():
         b = api.fft(x, v)
         torch.cuda.synchronize()
         assert torch.equal(a, b)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_multipass_forced_small(variant):
+    """The multi-pass path (global levels + LDS sub-blocks + tail) forced at
+    small N, where it uses 4..32-point sub-blocks and three global levels."""
+    for dtype, n in (("c64", 32), ("c64", 128), ("c64", 1024), ("c128", 256), ("c64", 4096)):
+        batch = 3
+        _say("forced multipass", dtype, "variant", variant, "n", n)
+        x = inputs.complex_normal(3000 + n, batch, n)
+        if dtype == "c64":
+            x = x.astype(np.complex64)
+        ref = truth(x, 4)
+        y = _run(x, variant, dtype, flags=4)
+        e = rel(y, ref)
+        assert e <= bound(variant, dtype == "c128", x, ref), (dtype, n, e)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_multipass_large(variant):
+    """Signals above the LDS capacity: 2^15 and 2^16 (FP32), 2^14 (FP64)."""
+    for dtype, n, batch in (("c64", 1 << 15, 2), ("c64", 1 << 16, 2), ("c128", 1 << 14, 2)):
+        _say("multipass", dtype, "variant", variant, "n", n)
+        x = inputs.complex_normal(4000 + n, batch, n)
+        if dtype == "c64":
+            x = x.astype(np.complex64)
+        ref = truth(x, 4)
+        y = _run(x, variant, dtype)
+        e = rel(y, ref)
+        b = bound(variant, dtype == "c128", x, ref)
+        if np.isfinite(b):
+            assert e <= b, (dtype, n, e, b)
