@@ -6,11 +6,12 @@ The torch-facing functions are imported lazily so that the input generators
 (``paper_1404_1810_amd.inputs``) and the build script work without a GPU.
 """
 
-__all__ = ["fft", "adjoint", "ifft", "amqft", "power_loss", "Plan", "AMQFTFunction", "build"]
+__all__ = ["fft", "adjoint", "ifft", "amqft", "power_loss", "Plan", "ManyPlan", "exec_graph", "AMQFTFunction", "build"]
 
 
 def __getattr__(name):
-    if name in ("fft", "adjoint", "ifft", "amqft", "power_loss", "Plan", "AMQFTFunction", "get_plan"):
+    if name in ("fft", "adjoint", "ifft", "amqft", "power_loss", "Plan", "AMQFTFunction", "get_plan", "ManyPlan",
+                "exec_graph"):
         from . import api
         return getattr(api, name)
     if name == "build":

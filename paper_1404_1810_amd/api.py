@@ -168,3 +168,76 @@ def power_loss(x: torch.Tensor, w: torch.Tensor, variant: int = 4):
     w = w.contiguous()
     dt, n, batch = _storage(x)
     return get_plan(n, batch, variant, dt, 0, x.device).power_loss_grad(x, w)
+
+
+class ManyPlan:
+    """amqft_plan_create_many: signals of different power-of-two lengths in one
+    packed buffer (signal i: lengths[i] points at complex element offsets[i];
+    offsets has count+1 entries).  Executed by one persistent launch for the
+    short lengths plus one launch sequence per long length class; the first
+    out-of-place execution autotunes the launch shapes."""
+
+    def __init__(self, lengths, offsets, variant: int = 4, dtype: int = _lib.C64, flags: int = 0):
+        import numpy as np
+        lib = _lib.load()
+        L = np.ascontiguousarray(lengths, dtype=np.int64)
+        O = np.ascontiguousarray(offsets, dtype=np.int64)
+        if O.shape[0] != L.shape[0] + 1:
+            raise ValueError("offsets needs count+1 entries")
+        h = ctypes.c_void_p()
+        _lib.check(lib.amqft_plan_create_many(ctypes.byref(h), int(L.shape[0]), ctypes.c_void_p(L.ctypes.data),
+                                              ctypes.c_void_p(O.ctypes.data), int(variant), int(dtype), int(flags)),
+                   "amqft_plan_create_many")
+        self._h = h
+        self.count = int(L.shape[0])
+        self.total = int(O[-1]) if O.shape[0] else 0
+        self.variant, self.dtype = int(variant), int(dtype)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.load().amqft_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            if self._h is not None and self._h.value and torch.cuda.is_available():
+                torch.cuda.synchronize()
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self) -> int:
+        sz = ctypes.c_size_t()
+        _lib.check(_lib.load().amqft_plan_workspace_size(self._h, ctypes.byref(sz)), "workspace_size")
+        return int(sz.value)
+
+    def exec(self, x: torch.Tensor, out: torch.Tensor | None = None, adjoint: bool = False,
+             graph: bool = False) -> torch.Tensor:
+        if not x.is_cuda or not x.is_contiguous():
+            raise ValueError("input must be a contiguous GPU tensor")
+        dt = _DTYPES.get(x.dtype)
+        npts = x.numel() // (2 if dt in (_lib.C32H, _lib.C32B) else 1)
+        if dt != self.dtype or npts < self.total:
+            raise ValueError("buffer does not match the plan")
+        y = torch.empty_like(x) if out is None else out
+        lib = _lib.load()
+        st = _stream_handle(x.device)
+        if graph:
+            rc = lib.amqft_exec_graph(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                      1 if adjoint else 0, st)
+            _lib.check(rc, "amqft_exec_graph")
+        else:
+            fn = lib.amqft_exec_adjoint if adjoint else lib.amqft_exec
+            _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), st), "amqft_exec")
+        return y
+
+
+def exec_graph(plan: Plan, x: torch.Tensor, out: torch.Tensor, adjoint: bool = False) -> torch.Tensor:
+    """Run a single-length plan through its captured HIP graph (captured on the
+    first call for this (x, out) pair)."""
+    plan._check_tensor(x, "input")
+    plan._check_tensor(out, "output")
+    _lib.check(_lib.load().amqft_exec_graph(plan.handle, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), 1 if adjoint else 0,
+                                            _stream_handle(x.device)), "amqft_exec_graph")
+    return out

@@ -3,10 +3,12 @@
 // error path can be exercised without a GPU.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -17,6 +19,26 @@
 #include "amqft_internal.h"
 
 using namespace amqft;
+
+namespace {
+
+// one length class of a many-length plan
+struct length_class {
+    int logn = 0;
+    int64_t count = 0;
+    amqft_plan sub = nullptr;     // single-length plan (LDS or multi-pass), NULL = persistent kernel
+    void* offsets_dev = nullptr;  // int64 offsets of the class's signals
+};
+
+struct graph_entry {
+    const void* in;
+    void* out;
+    int adjoint;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
 
 struct amqft_plan_s {
     int variant = 4;
@@ -36,6 +58,18 @@ struct amqft_plan_s {
     int64_t chunk = 0;
     void* ws[3] = {nullptr, nullptr, nullptr};
     size_t ws_bytes = 0;
+    const void* offsets = nullptr;  // per-signal offsets (sub-plans of a many-length plan)
+    // many-length plans
+    bool many = false;
+    int64_t count = 0;
+    std::vector<length_class> classes;
+    void* items_dev = nullptr;     // persistent work list (int4 per item)
+    void* poffsets_dev = nullptr;  // offsets in work-list order
+    int nitems = 0;
+    int grid = 0;  // persistent workgroups
+    bool tuned = false;
+    // captured graphs
+    std::vector<graph_entry> graphs;
 };
 
 namespace {
@@ -49,6 +83,7 @@ amqft_status hip_fail(hipError_t e) {
 
 bool valid_variant(int v) { return v >= 1 && v <= 8; }
 bool valid_dtype(int t) { return t >= 0 && t <= 3; }
+constexpr unsigned kAllFlags = AMQFT_FLAG_ONTHEFLY_CONSTANTS | AMQFT_FLAG_NO_AUTOTUNE | AMQFT_FLAG_FORCE_MULTIPASS;
 
 int log2_exact(int64_t n) {
     if (n < 1 || (n & (n - 1)) != 0) return -1;
@@ -101,10 +136,65 @@ amqft_status build_constants(amqft_plan_s* p, int log2n) {
     return AMQFT_OK;
 }
 
-amqft_status exec_common(amqft_plan p, const void* in, void* out, void* stream, bool adjoint) {
-    if (!p) return AMQFT_ERR_INVALID_ARG;
-    if (p->batch == 0) return AMQFT_OK;  // nothing to read or write; pointers may be NULL
-    if (!in || !out) return AMQFT_ERR_INVALID_ARG;
+amqft_status prime(int variant, int dtype) {
+    hipError_t e = prime_lds(variant, dtype);
+    if (e == hipSuccess) e = prime_multipass(variant, dtype);
+    return e == hipSuccess ? AMQFT_OK : hip_fail(e);
+}
+
+// ---------------------------------------------------------------------------
+// tuning cache: JSON lines {"key": "...", "value": N} in $AMQFT_TUNE_CACHE
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string arch_name(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    return a.substr(0, a.find(':'));
+}
+
+void tune_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("AMQFT_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        char key[400];
+        int v;
+        if (sscanf(line, " {\"key\": \"%399[^\"]\", \"value\": %d}", key, &v) == 2) g_tune[key] = v;
+    }
+    fclose(f);
+}
+
+bool tune_get(const std::string& key, int* v) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_load();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *v = it->second;
+    return true;
+}
+
+void tune_put(const std::string& key, int v) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_load();
+    g_tune[key] = v;
+    const char* path = getenv("AMQFT_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"key\": \"%s\", \"value\": %d}\n", key.c_str(), v);
+    fclose(f);
+}
+
+amqft_status exec_single(amqft_plan p, const void* in, void* out, hipStream_t stream, bool adjoint) {
+    if (p->batch == 0) return AMQFT_OK;
     if (p->multipass) {
         mp_launch m{};
         m.variant = p->variant;
@@ -123,7 +213,8 @@ amqft_status exec_common(amqft_plan p, const void* in, void* out, void* stream, 
         m.conj_in = adjoint;
         m.conj_out = adjoint;
         m.onthefly = (p->flags & AMQFT_FLAG_ONTHEFLY_CONSTANTS) != 0;
-        hipError_t e = launch_multipass(m, static_cast<hipStream_t>(stream));
+        m.offsets = p->offsets;
+        hipError_t e = launch_multipass(m, stream);
         return e == hipSuccess ? AMQFT_OK : hip_fail(e);
     }
     lds_launch a{};
@@ -138,15 +229,186 @@ amqft_status exec_common(amqft_plan p, const void* in, void* out, void* stream, 
     a.conj_in = adjoint;
     a.conj_out = adjoint;
     a.onthefly = (p->flags & AMQFT_FLAG_ONTHEFLY_CONSTANTS) != 0;
-    hipError_t e = launch_lds(a, static_cast<hipStream_t>(stream));
+    a.offsets = p->offsets;
+    hipError_t e = launch_lds(a, stream);
     return e == hipSuccess ? AMQFT_OK : hip_fail(e);
+}
+
+amqft_status exec_many(amqft_plan p, const void* in, void* out, hipStream_t stream, bool adjoint,
+                       bool persistent = true, bool classes = true) {
+    if (persistent && p->nitems > 0) {
+        persistent_launch a{};
+        a.variant = p->variant;
+        a.dtype = p->dtype;
+        a.in = in;
+        a.out = out;
+        a.ktab = p->ktab;
+        a.ktab_log2n = p->ktab_log2n;
+        a.items = p->items_dev;
+        a.nitems = p->nitems;
+        a.offsets = p->poffsets_dev;
+        a.grid = p->grid;
+        a.conj_in = adjoint;
+        a.conj_out = adjoint;
+        a.onthefly = (p->flags & AMQFT_FLAG_ONTHEFLY_CONSTANTS) != 0;
+        hipError_t e = launch_persistent(a, stream);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (!classes) return AMQFT_OK;
+    for (const length_class& c : p->classes) {
+        if (!c.sub) continue;
+        amqft_status st = exec_single(c.sub, in, out, stream, adjoint);
+        if (st != AMQFT_OK) return st;
+    }
+    return AMQFT_OK;
+}
+
+amqft_status exec_any(amqft_plan p, const void* in, void* out, hipStream_t stream, bool adjoint) {
+    return p->many ? exec_many(p, in, out, stream, adjoint) : exec_single(p, in, out, stream, adjoint);
+}
+
+// time one run of fn on stream s (ms), after one warm-up run
+template <typename F>
+amqft_status time_it(F fn, hipStream_t s, float* ms) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return AMQFT_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return AMQFT_ERR_HIP; }
+    amqft_status st = fn();
+    (void)hipEventRecord(e0, s);
+    if (st == AMQFT_OK) st = fn();
+    (void)hipEventRecord(e1, s);
+    hipError_t e = hipEventSynchronize(e1);
+    if (st == AMQFT_OK && e != hipSuccess) st = hip_fail(e);
+    if (st == AMQFT_OK) (void)hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+// Autotuning of a many-length plan on its first out-of-place execution: the
+// number of persistent workgroups and the sub-block size of each multi-pass
+// length class.  Every candidate computes the same transform, so the
+// buffers hold a valid result whichever candidate ran last.  Results are
+// cached per process and, with AMQFT_TUNE_CACHE set, in that file.
+amqft_status autotune(amqft_plan p, const void* in, void* out, hipStream_t user, bool adjoint) {
+    p->tuned = true;
+    if ((p->flags & AMQFT_FLAG_NO_AUTOTUNE) || in == out) return AMQFT_OK;
+    hipError_t e = hipStreamSynchronize(user);
+    if (e != hipSuccess) return hip_fail(e);
+    hipStream_t s;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e);
+    const std::string arch = arch_name(p->device);
+    char buf[400];
+    amqft_status st = AMQFT_OK;
+    if (p->nitems > 0) {
+        std::string hist;
+        for (const length_class& c : p->classes)
+            if (!c.sub) hist += std::to_string(c.logn) + ":" + std::to_string(c.count) + ",";
+        snprintf(buf, sizeof buf, "%s/v%d/t%d/persistent/%s", arch.c_str(), p->variant, p->dtype, hist.c_str());
+        int g;
+        if (tune_get(buf, &g)) {
+            p->grid = g;
+        } else {
+            int cus = 256;
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) cus = prop.multiProcessorCount;
+            const int cand[5] = {cus, 2 * cus, 4 * cus, 8 * cus, 16 * cus};
+            float best = 1e30f;
+            int bestg = p->grid;
+            for (int g2 : cand) {
+                p->grid = std::max(1, std::min(g2, p->nitems));
+                float ms = 0;
+                st = time_it([&] { return exec_many(p, in, out, s, adjoint, true, false); }, s, &ms);
+                if (st != AMQFT_OK) break;
+                if (ms < best) { best = ms; bestg = p->grid; }
+            }
+            p->grid = bestg;
+            if (st == AMQFT_OK) tune_put(buf, bestg);
+        }
+    }
+    for (length_class& c : p->classes) {
+        if (st != AMQFT_OK) break;
+        if (!c.sub || !c.sub->multipass) continue;
+        amqft_plan q = c.sub;
+        snprintf(buf, sizeof buf, "%s/v%d/t%d/multipass/logn%d", arch.c_str(), p->variant, p->dtype, c.logn);
+        int sbv;
+        if (tune_get(buf, &sbv)) {
+            q->sb = sbv;
+            continue;
+        }
+        const int hi = std::min(multipass_sb(q->dtype), q->logn - 3);
+        float best = 1e30f;
+        int bestsb = q->sb;
+        for (int cand = std::max(2, hi - 2); cand <= hi; ++cand) {
+            q->sb = cand;
+            float ms = 0;
+            st = time_it([&] { return exec_single(q, in, out, s, adjoint); }, s, &ms);
+            if (st != AMQFT_OK) break;
+            if (ms < best) { best = ms; bestsb = cand; }
+        }
+        q->sb = bestsb;
+        if (st == AMQFT_OK) tune_put(buf, bestsb);
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    return st;
+}
+
+amqft_status exec_common(amqft_plan p, const void* in, void* out, void* stream, bool adjoint) {
+    if (!p) return AMQFT_ERR_INVALID_ARG;
+    if ((p->many ? p->count : p->batch) == 0) return AMQFT_OK;  // nothing to read or write
+    if (!in || !out) return AMQFT_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->many && !p->tuned) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            amqft_status st = autotune(p, in, out, s, adjoint);
+            if (st != AMQFT_OK) return st;
+        }
+    }
+    return exec_any(p, in, out, s, adjoint);
+}
+
+amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int variant, int dtype, unsigned flags) {
+    const int logn = log2_exact(n);
+    const bool mp = logn > max_lds_log2(dtype) || (flags & AMQFT_FLAG_FORCE_MULTIPASS);
+    amqft_plan_s* p = new (std::nothrow) amqft_plan_s();
+    if (!p) return AMQFT_ERR_ALLOC;
+    p->variant = variant;
+    p->dtype = dtype;
+    p->flags = flags;
+    p->n = n;
+    p->logn = logn;
+    p->batch = batch;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { delete p; return hip_fail(e); }
+    amqft_status st = build_constants(p, logn);
+    if (st == AMQFT_OK) st = prime(variant, dtype);
+    if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
+    if (mp) {
+        p->multipass = true;
+        // forced (test) plans use small sub-blocks so that several global levels run
+        p->sb = (flags & AMQFT_FLAG_FORCE_MULTIPASS) ? std::max(2, std::min(multipass_sb(dtype), logn - 5))
+                                                     : std::min(multipass_sb(dtype), logn - 3);
+        const size_t per = multipass_ws_bytes_per_signal(logn, dtype);
+        const size_t cap = size_t(1) << 30;  // bytes per workspace buffer
+        p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per)));
+        p->ws_bytes = 3 * (size_t)p->chunk * per;
+        for (int i = 0; i < 3 && batch > 0; ++i) {
+            e = hipMalloc(&p->ws[i], (size_t)p->chunk * per);
+            if (e != hipSuccess) { p->ws[i] = nullptr; amqft_plan_destroy(p); return hip_fail(e); }
+        }
+    }
+    *out = p;
+    return AMQFT_OK;
 }
 
 }  // namespace
 
 extern "C" {
 
-const char* amqft_version(void) { return "amqft 0.1.0 (gfx950)"; }
+const char* amqft_version(void) { return "amqft 0.2.0 (gfx950)"; }
 
 const char* amqft_last_hip_error(void) { return g_hip_error.c_str(); }
 
@@ -167,42 +429,14 @@ amqft_status amqft_plan_create(amqft_plan* out, int64_t n, int64_t batch, amqft_
     if (!out) return AMQFT_ERR_INVALID_ARG;
     *out = nullptr;
     if (!valid_variant((int)variant) || !valid_dtype((int)dtype) || batch < 0) return AMQFT_ERR_INVALID_ARG;
-    if (flags & ~(unsigned)(AMQFT_FLAG_ONTHEFLY_CONSTANTS | AMQFT_FLAG_NO_AUTOTUNE | AMQFT_FLAG_FORCE_MULTIPASS))
-        return AMQFT_ERR_INVALID_ARG;
+    if (flags & ~kAllFlags) return AMQFT_ERR_INVALID_ARG;
     const int logn = log2_exact(n);
     if (logn < 0) return AMQFT_ERR_NOT_POW2;
     if (logn > AMQFT_MAX_LOG2N) return AMQFT_ERR_UNSUPPORTED;
     const bool mp = logn > max_lds_log2((int)dtype) || (flags & AMQFT_FLAG_FORCE_MULTIPASS);
     if (mp && logn < 5) return AMQFT_ERR_UNSUPPORTED;  // multi-pass needs a block of at least 8 points
     if (batch > (int64_t(1) << 40)) return AMQFT_ERR_UNSUPPORTED;
-    amqft_plan_s* p = new (std::nothrow) amqft_plan_s();
-    if (!p) return AMQFT_ERR_ALLOC;
-    p->variant = (int)variant;
-    p->dtype = (int)dtype;
-    p->flags = flags;
-    p->n = n;
-    p->logn = logn;
-    p->batch = batch;
-    hipError_t e = hipGetDevice(&p->device);
-    if (e != hipSuccess) { delete p; return hip_fail(e); }
-    amqft_status st = build_constants(p, logn);
-    if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
-    if (mp) {
-        p->multipass = true;
-        // forced (test) plans use small sub-blocks so that several global levels run
-        p->sb = (flags & AMQFT_FLAG_FORCE_MULTIPASS) ? std::max(2, std::min(multipass_sb((int)dtype), logn - 5))
-                                                     : std::min(multipass_sb((int)dtype), logn - 3);
-        const size_t per = multipass_ws_bytes_per_signal(logn, (int)dtype);
-        const size_t cap = size_t(1) << 30;  // bytes per workspace buffer
-        p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per)));
-        p->ws_bytes = 3 * (size_t)p->chunk * per;
-        for (int i = 0; i < 3 && batch > 0; ++i) {
-            hipError_t e = hipMalloc(&p->ws[i], (size_t)p->chunk * per);
-            if (e != hipSuccess) { p->ws[i] = nullptr; amqft_plan_destroy(p); return hip_fail(e); }
-        }
-    }
-    *out = p;
-    return AMQFT_OK;
+    return create_single(out, n, batch, (int)variant, (int)dtype, flags);
 }
 
 amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_t* lengths_host,
@@ -212,17 +446,92 @@ amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_
     *out = nullptr;
     if (!valid_variant((int)variant) || !valid_dtype((int)dtype) || count < 0) return AMQFT_ERR_INVALID_ARG;
     if (count > 0 && (!lengths_host || !offsets_host)) return AMQFT_ERR_INVALID_ARG;
-    if (flags & ~(unsigned)(AMQFT_FLAG_ONTHEFLY_CONSTANTS | AMQFT_FLAG_NO_AUTOTUNE | AMQFT_FLAG_FORCE_MULTIPASS))
-        return AMQFT_ERR_INVALID_ARG;
+    if (flags & ~kAllFlags) return AMQFT_ERR_INVALID_ARG;
+    int maxlog = 2;
     for (int64_t i = 0; i < count; ++i) {
         const int l = log2_exact(lengths_host[i]);
         if (l < 0) return AMQFT_ERR_NOT_POW2;
         if (l > AMQFT_MAX_LOG2N) return AMQFT_ERR_UNSUPPORTED;
+        maxlog = std::max(maxlog, l);
     }
     if (count > 0 && offsets_host[0] < 0) return AMQFT_ERR_INVALID_ARG;
     for (int64_t i = 0; i < count; ++i)
         if (offsets_host[i + 1] - offsets_host[i] < lengths_host[i]) return AMQFT_ERR_INVALID_ARG;
-    return AMQFT_ERR_UNSUPPORTED;
+
+    amqft_plan_s* p = new (std::nothrow) amqft_plan_s();
+    if (!p) return AMQFT_ERR_ALLOC;
+    p->variant = (int)variant;
+    p->dtype = (int)dtype;
+    p->flags = flags & ~(unsigned)AMQFT_FLAG_FORCE_MULTIPASS;
+    p->many = true;
+    p->count = count;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { delete p; return hip_fail(e); }
+    amqft_status st = build_constants(p, maxlog);
+    if (st == AMQFT_OK) st = prime((int)variant, (int)dtype);
+    if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
+
+    // group the signals by length
+    std::vector<std::vector<int64_t>> by(AMQFT_MAX_LOG2N + 1);
+    for (int64_t i = 0; i < count; ++i) by[log2_exact(lengths_host[i])].push_back(offsets_host[i]);
+    // persistent work list: lengths up to kPersistentMaxLog2, items of up to
+    // 256/T signals of one length, longest length first
+    std::vector<int> items;  // 4 ints per item
+    std::vector<long long> poffs;
+    for (int l = kPersistentMaxLog2; l >= 0; --l) {
+        const std::vector<int64_t>& v = by[l];
+        if (v.empty()) continue;
+        length_class c;
+        c.logn = l;
+        c.count = (int64_t)v.size();
+        p->classes.push_back(c);
+        const int N = 1 << l;
+        const int T = (N >> 4) > 1 ? (N >> 4) : 1;
+        const int spw = l <= 1 ? 256 : 256 / T;
+        for (size_t s0 = 0; s0 < v.size(); s0 += spw) {
+            const int cnt = (int)std::min<size_t>(spw, v.size() - s0);
+            items.push_back(l);
+            items.push_back((int)poffs.size());
+            items.push_back(cnt);
+            items.push_back(0);
+            for (int u = 0; u < cnt; ++u) poffs.push_back(v[s0 + u]);
+        }
+    }
+    p->nitems = (int)(items.size() / 4);
+    if (p->nitems > 0) {
+        e = hipMalloc(&p->items_dev, items.size() * sizeof(int));
+        if (e == hipSuccess)
+            e = hipMemcpy(p->items_dev, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&p->poffsets_dev, poffs.size() * sizeof(long long));
+        if (e == hipSuccess)
+            e = hipMemcpy(p->poffsets_dev, poffs.data(), poffs.size() * sizeof(long long), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { amqft_plan_destroy(p); return hip_fail(e); }
+        int cus = 256;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) cus = prop.multiProcessorCount;
+        p->grid = std::max(1, std::min(4 * cus, p->nitems));
+    }
+    // longer lengths: one single-length plan per class over the packed buffer
+    for (int l = kPersistentMaxLog2 + 1; l <= AMQFT_MAX_LOG2N; ++l) {
+        const std::vector<int64_t>& v = by[l];
+        if (v.empty()) continue;
+        length_class c;
+        c.logn = l;
+        c.count = (int64_t)v.size();
+        st = create_single(&c.sub, int64_t(1) << l, c.count, p->variant, p->dtype, p->flags);
+        if (st == AMQFT_OK) {
+            e = hipMalloc(&c.offsets_dev, v.size() * sizeof(int64_t));
+            if (e == hipSuccess)
+                e = hipMemcpy(c.offsets_dev, v.data(), v.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+            if (e != hipSuccess) st = hip_fail(e);
+            else c.sub->offsets = c.offsets_dev;
+        }
+        p->classes.push_back(c);
+        if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
+        p->ws_bytes += c.sub->ws_bytes;
+    }
+    *out = p;
+    return AMQFT_OK;
 }
 
 amqft_status amqft_exec(amqft_plan p, const void* in, void* out, void* stream) {
@@ -236,6 +545,7 @@ amqft_status amqft_exec_adjoint(amqft_plan p, const void* in, void* out, void* s
 amqft_status amqft_power_loss_grad(amqft_plan p, const void* x, const void* w, void* grad, void* loss,
                                    void* stream) {
     if (!p) return AMQFT_ERR_INVALID_ARG;
+    if (p->many) return AMQFT_ERR_UNSUPPORTED;
     if (p->batch == 0) return AMQFT_OK;
     if (!x || !w || !grad || !loss) return AMQFT_ERR_INVALID_ARG;
     if (p->logn < 2 || p->multipass) return AMQFT_ERR_UNSUPPORTED;
@@ -256,13 +566,61 @@ amqft_status amqft_power_loss_grad(amqft_plan p, const void* x, const void* w, v
 }
 
 amqft_status amqft_exec_graph(amqft_plan p, const void* in, void* out, int adjoint, void* stream) {
-    if (!p || !in || !out) return AMQFT_ERR_INVALID_ARG;
-    (void)adjoint; (void)stream;
-    return AMQFT_ERR_UNSUPPORTED;
+    if (!p) return AMQFT_ERR_INVALID_ARG;
+    if ((p->many ? p->count : p->batch) == 0) return AMQFT_OK;
+    if (!in || !out) return AMQFT_ERR_INVALID_ARG;
+    hipStream_t user = static_cast<hipStream_t>(stream);
+    graph_entry* g = nullptr;
+    for (graph_entry& ge : p->graphs)
+        if (ge.in == in && ge.out == out && ge.adjoint == (adjoint != 0)) g = &ge;
+    if (!g) {
+        // tuning synchronises and times candidates, so it happens before capture
+        if (p->many && !p->tuned) {
+            amqft_status st = autotune(p, in, out, user, adjoint != 0);
+            if (st != AMQFT_OK) return st;
+        }
+        hipStream_t cs;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e);
+        graph_entry ne{in, out, adjoint != 0, nullptr, nullptr};
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        amqft_status st = AMQFT_OK;
+        if (e == hipSuccess) {
+            st = exec_any(p, in, out, cs, adjoint != 0);
+            hipError_t e2 = hipStreamEndCapture(cs, &ne.graph);
+            if (st == AMQFT_OK && e2 != hipSuccess) st = hip_fail(e2);
+        } else {
+            st = hip_fail(e);
+        }
+        if (st == AMQFT_OK) {
+            e = hipGraphInstantiate(&ne.exec, ne.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) st = hip_fail(e);
+        }
+        (void)hipStreamDestroy(cs);
+        if (st != AMQFT_OK) {
+            if (ne.exec) (void)hipGraphExecDestroy(ne.exec);
+            if (ne.graph) (void)hipGraphDestroy(ne.graph);
+            return st;
+        }
+        p->graphs.push_back(ne);
+        g = &p->graphs.back();
+    }
+    hipError_t e = hipGraphLaunch(g->exec, user);
+    return e == hipSuccess ? AMQFT_OK : hip_fail(e);
 }
 
 amqft_status amqft_plan_destroy(amqft_plan p) {
     if (!p) return AMQFT_OK;
+    for (graph_entry& g : p->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    for (length_class& c : p->classes) {
+        if (c.sub) amqft_plan_destroy(c.sub);
+        if (c.offsets_dev) (void)hipFree(c.offsets_dev);
+    }
+    if (p->items_dev) (void)hipFree(p->items_dev);
+    if (p->poffsets_dev) (void)hipFree(p->poffsets_dev);
     if (p->ktab) (void)hipFree(p->ktab);
     for (void* w : p->ws)
         if (w) (void)hipFree(w);

@@ -24,7 +24,26 @@ struct lds_launch {
     int conj_in;       // conjugate the input on load
     int conj_out;      // conjugate the output on store
     int onthefly;      // generate constants on the device (FP64) instead
+    const void* offsets = nullptr;  // device int64 offsets (complex elements) per signal, or NULL = stride N
 };
+
+// Largest log2(N) handled by the persistent many-length kernel (256 threads).
+constexpr int kPersistentMaxLog2 = 12;
+
+struct persistent_launch {
+    int variant, dtype;
+    const void* in;
+    void* out;
+    const void* ktab;
+    int ktab_log2n;
+    const void* items;    // device int4 {log2 N, first offset index, count, 0}
+    int nitems;
+    const void* offsets;  // device int64 signal offsets, grouped per item
+    int grid;             // persistent workgroups
+    int conj_in, conj_out, onthefly;
+};
+hipError_t launch_persistent(const persistent_launch& a, hipStream_t stream);
+size_t persistent_lds_bytes(int dtype);
 
 struct loss_launch {
     int variant, dtype, logn;  // logn >= 2
@@ -58,12 +77,18 @@ struct mp_launch {
     const void* ktab;
     int ktab_log2n;
     int conj_in, conj_out, onthefly;
+    const void* offsets = nullptr;  // device int64 per-signal offsets, or NULL = stride N
 };
 hipError_t launch_multipass(const mp_launch& m, hipStream_t stream);
 // default sub-block exponent for a storage type (largest the LDS engine holds)
 int multipass_sb(int dtype);
 // bytes of one workspace buffer per signal
 size_t multipass_ws_bytes_per_signal(int logn, int dtype);
+
+// Raise the dynamic-LDS limit of the kernels of a variant/dtype (done at plan
+// creation so that no attribute call happens during graph capture).
+hipError_t prime_lds(int variant, int dtype);
+hipError_t prime_multipass(int variant, int dtype);
 
 // Bytes of dynamic LDS and threads per workgroup the LDS engine uses.
 void lds_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);

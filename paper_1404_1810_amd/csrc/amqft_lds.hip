@@ -2,6 +2,8 @@
 // workgroup, the whole recursion of Sec. 4 and 6 flattened into
 // level-synchronous passes over the signal held in LDS (layout and level
 // functions in amqft_levels.h).
+#include <algorithm>
+
 #include "amqft_device.h"
 #include "amqft_internal.h"
 #include "amqft_levels.h"
@@ -16,7 +18,8 @@ using namespace lv;
 template <int V, typename S>
 __global__ __launch_bounds__(1024) void amqft_lds_kernel(const S* __restrict__ in, S* __restrict__ out,
                                                           const typename storage<S>::R* __restrict__ ktab,
-                                                          int logn, long long batch, int kshift, int flags) {
+                                                          int logn, long long batch, int kshift, int flags,
+                                                          const long long* __restrict__ offsets) {
     using R = typename storage<S>::R;
     using VT = variant_traits<V>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -35,8 +38,9 @@ __global__ __launch_bounds__(1024) void amqft_lds_kernel(const S* __restrict__ i
     const size_t kt_bytes = ((size_t)Q * sizeof(R) + 15) & ~(size_t)15;
     cx<R>* w = reinterpret_cast<cx<R>*>(smem + kt_bytes) + (size_t)slot * (N + T);
     cx<R>* scr = w + N;
-    const S* x = in + (valid ? sig : 0) * (long long)N;
-    S* y = out + (valid ? sig : 0) * (long long)N;
+    const long long base = valid ? (offsets ? offsets[sig] : sig * (long long)N) : 0;
+    const S* x = in + base;
+    S* y = out + base;
 
     load_constants<V, R>(kt, ktab, Q, kshift, onthefly, logn);
     load_signal<VT::skel_a, S, R>(w, x, ltid, T, D, H, conj_in, valid);
@@ -146,23 +150,74 @@ __global__ __launch_bounds__(1024) void amqft_loss_kernel(const S* __restrict__ 
 
 // N = 1 (identity) and N = 2 (direct definition of the CDFT, Sec. 4)
 template <typename S>
-__global__ void amqft_tiny_kernel(const S* __restrict__ in, S* __restrict__ out, int logn, long long batch,
-                                  int flags) {
+__device__ void tiny_one(const S* x, S* y, int logn, bool conj_in, bool conj_out) {
     using R = typename storage<S>::R;
-    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
-    const bool conj_in = flags & 1, conj_out = flags & 2;
     if (logn == 0) {
-        cx<R> a = storage<S>::ld(in + b);
+        cx<R> a = storage<S>::ld(x);
         if (conj_in != conj_out) a = cconj(a);
-        storage<S>::st(out + b, a);
+        storage<S>::st(y, a);
     } else {
-        cx<R> a = storage<S>::ld(in + 2 * b), c = storage<S>::ld(in + 2 * b + 1);
+        cx<R> a = storage<S>::ld(x), c = storage<S>::ld(x + 1);
         if (conj_in) { a = cconj(a); c = cconj(c); }
         cx<R> s0 = a + c, s1 = a - c;
         if (conj_out) { s0 = cconj(s0); s1 = cconj(s1); }
-        storage<S>::st(out + 2 * b, s0);
-        storage<S>::st(out + 2 * b + 1, s1);
+        storage<S>::st(y, s0);
+        storage<S>::st(y + 1, s1);
+    }
+}
+
+template <typename S>
+__global__ void amqft_tiny_kernel(const S* __restrict__ in, S* __restrict__ out, int logn, long long batch,
+                                  int flags, const long long* __restrict__ offsets) {
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const long long base = offsets ? offsets[b] : (b << logn);
+    tiny_one<S>(in + base, out + base, logn, flags & 1, flags & 2);
+}
+
+// ---------------------------------------------------------------------------
+// persistent kernel for many signals of different lengths (N <= 4096): the
+// work list holds items (log2 N, first entry of the offset list, count);
+// workgroup g takes items g, g + gridDim.x, ... (the list is sorted by cost,
+// largest first, so the static round robin balances like longest-first).
+// Each item is up to 256/T signals of one length, T = max(1, N/16).
+// ---------------------------------------------------------------------------
+template <int V, typename S>
+__global__ __launch_bounds__(256) void amqft_persistent_kernel(const S* __restrict__ in, S* __restrict__ out,
+                                                                const typename storage<S>::R* __restrict__ ktab,
+                                                                int ktab_log2n, const int4* __restrict__ items,
+                                                                int nitems, const long long* __restrict__ offsets,
+                                                                int flags) {
+    using R = typename storage<S>::R;
+    using VT = variant_traits<V>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const bool conj_in = flags & 1, conj_out = flags & 2, onthefly = flags & 4;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w4 = items[it];
+        const int logn = w4.x, first = w4.y, count = w4.z;
+        if (logn <= 1) {
+            for (int u = threadIdx.x; u < count; u += blockDim.x) {
+                const long long o = offsets[first + u];
+                tiny_one<S>(in + o, out + o, logn, conj_in, conj_out);
+            }
+            continue;
+        }
+        const int N = 1 << logn, H = N >> 1, D = logn - 2, Q = 1 << D;
+        const int T = (N >> 4) > 1 ? (N >> 4) : 1;
+        const int slot = threadIdx.x / T;
+        const int ltid = threadIdx.x - slot * T;
+        const bool valid = slot < count;
+        R* kt = reinterpret_cast<R*>(smem);
+        const size_t kt_bytes = ((size_t)(1 << 10) * sizeof(R) + 15) & ~(size_t)15;  // up to N = 4096
+        cx<R>* w = reinterpret_cast<cx<R>*>(smem + kt_bytes) + (size_t)slot * (N + T);
+        cx<R>* scr = w + N;
+        const long long o = valid ? offsets[first + slot] : 0;
+        load_constants<V, R>(kt, ktab, Q, ktab_log2n - logn, onthefly, logn);
+        load_signal<VT::skel_a, S, R>(w, in + o, ltid, T, D, H, conj_in, valid);
+        __syncthreads();
+        core<V, R>(w, kt, scr, ltid, T, D, H);
+        store_signal<S, R>(w, out + o, ltid, T, H, conj_out, valid);
+        __syncthreads();
     }
 }
 
@@ -187,7 +242,8 @@ static hipError_t launch_typed(const lds_launch& a, hipStream_t stream) {
         const int tpb = 256;
         const long long grid = (a.batch + tpb - 1) / tpb;
         hipLaunchKernelGGL(amqft_tiny_kernel<S>, dim3((unsigned)grid), dim3(tpb), 0, stream,
-                           static_cast<const S*>(a.in), static_cast<S*>(a.out), a.logn, (long long)a.batch, flags);
+                           static_cast<const S*>(a.in), static_cast<S*>(a.out), a.logn, (long long)a.batch, flags,
+                           static_cast<const long long*>(a.offsets));
         return hipGetLastError();
     }
     int threads, spw;
@@ -204,7 +260,7 @@ static hipError_t launch_typed(const lds_launch& a, hipStream_t stream) {
     const int kshift = a.ktab_log2n - a.logn;
     hipLaunchKernelGGL((amqft_lds_kernel<V, S>), dim3((unsigned)grid), dim3(threads), lds, stream,
                        static_cast<const S*>(a.in), static_cast<S*>(a.out), static_cast<const R*>(a.ktab), a.logn,
-                       (long long)a.batch, kshift, flags);
+                       (long long)a.batch, kshift, flags, static_cast<const long long*>(a.offsets));
     return hipGetLastError();
 }
 
@@ -254,6 +310,60 @@ hipError_t launch_loss(const loss_launch& a, hipStream_t s) {
     }
 }
 
+size_t persistent_lds_bytes(int dtype) {
+    const size_t rsz = dtype == 0 ? 8 : 4;
+    const size_t kt_bytes = ((size_t)(1 << 10) * rsz + 15) & ~(size_t)15;
+    size_t m = 0;
+    for (int logn = 2; logn <= kPersistentMaxLog2; ++logn) {
+        const int N = 1 << logn, T = (N >> 4) > 1 ? (N >> 4) : 1, spw = 256 / T;
+        m = std::max(m, (size_t)spw * (N + T) * 2 * rsz);
+    }
+    return kt_bytes + m;
+}
+
+template <int V, typename S>
+static hipError_t launch_persistent_typed(const persistent_launch& a, hipStream_t stream) {
+    using R = typename storage<S>::R;
+    if (a.nitems <= 0) return hipSuccess;
+    const size_t lds = persistent_lds_bytes(a.dtype);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_persistent_kernel<V, S>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int flags = (a.conj_in ? 1 : 0) | (a.conj_out ? 2 : 0) | (a.onthefly ? 4 : 0);
+    hipLaunchKernelGGL((amqft_persistent_kernel<V, S>), dim3((unsigned)a.grid), dim3(256), lds, stream,
+                       static_cast<const S*>(a.in), static_cast<S*>(a.out), static_cast<const R*>(a.ktab),
+                       a.ktab_log2n, static_cast<const int4*>(a.items), a.nitems,
+                       static_cast<const long long*>(a.offsets), flags);
+    return hipGetLastError();
+}
+
+template <int V>
+static hipError_t launch_persistent_v(const persistent_launch& a, hipStream_t s) {
+    switch (a.dtype) {
+    case 0: return launch_persistent_typed<V, double2>(a, s);
+    case 1: return launch_persistent_typed<V, float2>(a, s);
+    case 2: return launch_persistent_typed<V, __half2>(a, s);
+    default: return launch_persistent_typed<V, bf16x2>(a, s);
+    }
+}
+
+hipError_t launch_persistent(const persistent_launch& a, hipStream_t s) {
+    switch (a.variant) {
+    case 1: return launch_persistent_v<1>(a, s);
+    case 2: return launch_persistent_v<2>(a, s);
+    case 3: return launch_persistent_v<3>(a, s);
+    case 4: return launch_persistent_v<4>(a, s);
+    case 5: return launch_persistent_v<5>(a, s);
+    case 6: return launch_persistent_v<6>(a, s);
+    case 7: return launch_persistent_v<7>(a, s);
+    default: return launch_persistent_v<8>(a, s);
+    }
+}
+
 template <int V>
 static hipError_t launch_v(const lds_launch& a, hipStream_t s) {
     switch (a.dtype) {
@@ -261,6 +371,43 @@ static hipError_t launch_v(const lds_launch& a, hipStream_t s) {
     case 1: return launch_typed<V, float2>(a, s);
     case 2: return launch_typed<V, __half2>(a, s);
     default: return launch_typed<V, bf16x2>(a, s);
+    }
+}
+
+// set the dynamic-LDS limit of every kernel a plan may launch (before any
+// graph capture, since attribute calls are not stream work)
+template <int V, typename S>
+static hipError_t prime_typed() {
+    const void* ks[3] = {reinterpret_cast<const void*>(&amqft_lds_kernel<V, S>),
+                         reinterpret_cast<const void*>(&amqft_loss_kernel<V, S>),
+                         reinterpret_cast<const void*>(&amqft_persistent_kernel<V, S>)};
+    for (const void* k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int V>
+static hipError_t prime_v(int dtype) {
+    switch (dtype) {
+    case 0: return prime_typed<V, double2>();
+    case 1: return prime_typed<V, float2>();
+    case 2: return prime_typed<V, __half2>();
+    default: return prime_typed<V, bf16x2>();
+    }
+}
+
+hipError_t prime_lds(int variant, int dtype) {
+    switch (variant) {
+    case 1: return prime_v<1>(dtype);
+    case 2: return prime_v<2>(dtype);
+    case 3: return prime_v<3>(dtype);
+    case 4: return prime_v<4>(dtype);
+    case 5: return prime_v<5>(dtype);
+    case 6: return prime_v<6>(dtype);
+    case 7: return prime_v<7>(dtype);
+    default: return prime_v<8>(dtype);
     }
 }
 

@@ -294,14 +294,15 @@ __global__ __launch_bounds__(1024) void mp_lds_kernel(cx<R>* __restrict__ ws, co
 // load with D_c/D_r (placement of skeleton A or natural order of B)
 template <bool SKEL_A, typename S>
 __global__ __launch_bounds__(256) void mp_load_kernel(const S* __restrict__ in, cx<typename storage<S>::R>* __restrict__ ws,
-                                                      int logn, long long nsig, int conj) {
+                                                      int logn, long long nsig, int conj,
+                                                      const long long* __restrict__ offsets) {
     using R = typename storage<S>::R;
     const int N = 1 << logn, H = N >> 1, D = logn - 2;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= nsig * H) return;
     const long long sig = gid / H;
     const int m = (int)(gid - sig * H);
-    const S* x = in + sig * N;
+    const S* x = in + (offsets ? offsets[sig] : sig * N);
     cx<R>* w = ws + sig * N;
     cx<R> a = storage<S>::ld(x + (m == 0 ? 0 : m));
     cx<R> b = storage<S>::ld(x + (m == 0 ? H : N - m));
@@ -323,7 +324,8 @@ __global__ __launch_bounds__(256) void mp_load_kernel(const S* __restrict__ in, 
 // D_c combine and store
 template <typename S>
 __global__ __launch_bounds__(256) void mp_store_kernel(const cx<typename storage<S>::R>* __restrict__ ws, S* __restrict__ out,
-                                                       int logn, long long nsig, int conj) {
+                                                       int logn, long long nsig, int conj,
+                                                       const long long* __restrict__ offsets) {
     using R = typename storage<S>::R;
     const int N = 1 << logn, H = N >> 1;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(256) void mp_store_kernel(const cx<typename storage
     const long long sig = gid / H;
     const int k = (int)(gid - sig * H);
     const cx<R>* w = ws + sig * N;
-    S* y = out + sig * N;
+    S* y = out + (offsets ? offsets[sig] : sig * N);
     if (k == 0) {
         cx<R> a = w[0], b = w[H];
         if (conj) { a = cconj(a); b = cconj(b); }
@@ -391,15 +393,16 @@ hipError_t run_typed(const mp_launch& m, hipStream_t st) {
     hipError_t e;
     for (long long s0 = 0; s0 < m.batch; s0 += m.chunk) {
         const long long ns = std::min<long long>(m.chunk, m.batch - s0);
-        const S* in = static_cast<const S*>(m.in) + (s0 << logn);
-        S* out = static_cast<S*>(m.out) + (s0 << logn);
+        const long long* offs = m.offsets ? static_cast<const long long*>(m.offsets) + s0 : nullptr;
+        const S* in = static_cast<const S*>(m.in) + (offs ? 0 : (s0 << logn));
+        S* out = static_cast<S*>(m.out) + (offs ? 0 : (s0 << logn));
         cx<R>* a = static_cast<cx<R>*>(m.ws0);
         cx<R>* b = static_cast<cx<R>*>(m.ws1);
         cx<R>* tmp = static_cast<cx<R>*>(m.ws2);
         {
             const long long total = ns << (logn - 1);
             hipLaunchKernelGGL((mp_load_kernel<VT::skel_a, S>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                               st, in, a, logn, ns, m.conj_in);
+                               st, in, a, logn, ns, m.conj_in, offs);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         if constexpr (VT::skel_a) {
@@ -432,7 +435,7 @@ hipError_t run_typed(const mp_launch& m, hipStream_t st) {
         {
             const long long total = ns << (logn - 1);
             hipLaunchKernelGGL((mp_store_kernel<S>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a,
-                               out, logn, ns, m.conj_out);
+                               out, logn, ns, m.conj_out, offs);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
@@ -456,6 +459,26 @@ int multipass_sb(int dtype) { return dtype == 0 ? kMaxLdsLog2F64 - 2 : kMaxLdsLo
 size_t multipass_ws_bytes_per_signal(int logn, int dtype) {
     const size_t r = dtype == 0 ? 16 : 8;
     return ((size_t)1 << logn) * r;
+}
+
+template <int V>
+static hipError_t prime_mp_v(int dtype) {
+    const void* k = dtype == 0 ? reinterpret_cast<const void*>(&mp_lds_kernel<V, double>)
+                               : reinterpret_cast<const void*>(&mp_lds_kernel<V, float>);
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+hipError_t prime_multipass(int variant, int dtype) {
+    switch (variant) {
+    case 1: return prime_mp_v<1>(dtype);
+    case 2: return prime_mp_v<2>(dtype);
+    case 3: return prime_mp_v<3>(dtype);
+    case 4: return prime_mp_v<4>(dtype);
+    case 5: return prime_mp_v<5>(dtype);
+    case 6: return prime_mp_v<6>(dtype);
+    case 7: return prime_mp_v<7>(dtype);
+    default: return prime_mp_v<8>(dtype);
+    }
 }
 
 hipError_t launch_multipass(const mp_launch& m, hipStream_t st) {
