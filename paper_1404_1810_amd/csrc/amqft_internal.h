@@ -25,6 +25,7 @@ struct lds_launch {
     int conj_out;      // conjugate the output on store
     int onthefly;      // generate constants on the device (FP64) instead
     const void* offsets = nullptr;  // device int64 offsets (complex elements) per signal, or NULL = stride N
+    int generic = 0;                // 1: always use the generic engine (tests of that path)
 };
 
 // Largest log2(N) handled by the persistent many-length kernel (256 threads).
@@ -59,6 +60,10 @@ struct loss_launch {
 
 // Fused loss/gradient kernel (forward, |w|^2 weighting, adjoint).
 hipError_t launch_loss(const loss_launch& a, hipStream_t stream);
+
+// Fast kernels with compile-time geometry (N = 64 .. 4096, FP32 / FP64).
+bool fast_supported(int logn, int dtype);
+hipError_t launch_fast(const lds_launch& a, hipStream_t stream);
 
 // Launch the LDS-resident engine; returns the hipError_t of the launch.
 hipError_t launch_lds(const lds_launch& a, hipStream_t stream);

@@ -412,6 +412,7 @@ hipError_t prime_lds(int variant, int dtype) {
 }
 
 hipError_t launch_lds(const lds_launch& a, hipStream_t s) {
+    if (!a.generic && fast_supported(a.logn, a.dtype)) return launch_fast(a, s);
     switch (a.variant) {
     case 1: return launch_v<1>(a, s);
     case 2: return launch_v<2>(a, s);

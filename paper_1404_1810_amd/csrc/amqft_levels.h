@@ -27,6 +27,15 @@ namespace lv {
 
 constexpr int KMAX = 8;  // items per thread per level
 
+// LDS address of signal position p: identity, or one pad slot per 16 points
+// (keeps the 16-point leaves of the fast kernel free of bank conflicts)
+struct ad_identity {
+    static __device__ __forceinline__ int at(int p) { return p; }
+};
+struct ad_pad16 {
+    static __device__ __forceinline__ int at(int p) { return p + (p >> 4); }
+};
+
 struct item {
     int side;   // 0 = DCT side, 1 = DST side
     int hb;     // log2 of h
@@ -38,12 +47,12 @@ struct item {
     bool active;
 };
 
-__device__ __forceinline__ item decode(int t, int D, int l, int H, bool switches) {
+__device__ __forceinline__ item decode(int t, int D, int l, int H, bool switches, int min_hb = 0) {
     item it;
     it.side = t >> D;
     const int tt = t & ((1 << D) - 1);
-    it.active = tt >= (1 << l);
     const int b = 31 - __clz(tt | 1);
+    it.active = tt >= (1 << l) && (b - l) >= min_hb;
     const int u = tt - (1 << b);
     it.hb = b - l;
     it.h = 1 << (it.hb < 0 ? 0 : it.hb);
@@ -64,7 +73,7 @@ __device__ __forceinline__ int kidx(int i, int hb, int D) { return (2 * i + 1) <
 // Skeleton A places c(m), m = 2^j (2i+1), at block j slot i (the odd-n part
 // that the D_n chain hands to dct_ot[N/2^j]); skeleton B keeps natural order.
 // ---------------------------------------------------------------------------
-template <bool SKEL_A, typename S, typename R>
+template <bool SKEL_A, typename S, typename R, typename AD = ad_identity>
 __device__ void load_signal(cx<R>* w, const S* x, int ltid, int T, int D, int H, bool conj, bool valid) {
     if (!valid) return;
     for (int m = ltid; m < H; m += T) {
@@ -72,16 +81,16 @@ __device__ void load_signal(cx<R>* w, const S* x, int ltid, int T, int D, int H,
         cx<R> b = storage<S>::ld(x + (m == 0 ? H : 2 * H - m));
         if (conj) { a = cconj(a); b = cconj(b); }
         if (m == 0) {
-            w[0] = a;  // c(0)
-            w[H] = b;  // c(N/2)
+            w[AD::at(0)] = a;  // c(0)
+            w[AD::at(H)] = b;  // c(N/2)
         } else {
             int pos = m;
             if (SKEL_A) {
                 const int j = __ffs(m) - 1;
                 pos = (1 << (D - j)) + (m >> (j + 1));
             }
-            w[pos] = a + b;
-            w[H + pos] = a - b;
+            w[AD::at(pos)] = a + b;
+            w[AD::at(H + pos)] = a - b;
         }
     }
 }
@@ -90,17 +99,17 @@ __device__ void load_signal(cx<R>* w, const S* x, int ltid, int T, int D, int H,
 // D_c^F and store: X(k) = C(k) - i D(k), X(N-k) = C(k) + i D(k) (eqs.
 // qft_17-21 with the sign of qft_19A corrected), X(0) = C(0), X(N/2) = C(N/2)
 // ---------------------------------------------------------------------------
-template <typename S, typename R>
+template <typename S, typename R, typename AD = ad_identity>
 __device__ void store_signal(const cx<R>* w, S* y, int ltid, int T, int H, bool conj, bool valid) {
     if (!valid) return;
     for (int k = ltid; k < H; k += T) {
         if (k == 0) {
-            cx<R> a = w[0], b = w[H];
+            cx<R> a = w[AD::at(0)], b = w[AD::at(H)];
             if (conj) { a = cconj(a); b = cconj(b); }
             storage<S>::st(y, a);
             storage<S>::st(y + H, b);
         } else {
-            const cx<R> C = w[k], Dd = w[H + k];
+            const cx<R> C = w[AD::at(k)], Dd = w[AD::at(H + k)];
             cx<R> xk = {C.re + Dd.im, C.im - Dd.re};
             cx<R> xnk = {C.re - Dd.im, C.im + Dd.re};
             if (conj) { xk = cconj(xk); xnk = cconj(xnk); }
@@ -116,8 +125,8 @@ __device__ void store_signal(const cx<R>* w, S* y, int ltid, int T, int H, bool 
 //   M^T (M1, M4, M5, M8): o times 2cos, 1/(2cos), 2sin, 1/(2sin) of theta*n
 //   (Tables tab:DCT/DST_odd_transformations); L = 8 base: o * cos(pi/4).
 // ---------------------------------------------------------------------------
-template <int V, typename R>
-__device__ void a_fwd_level(cx<R>* w, const R* kt, int ltid, int T, int D, int H, int l) {
+template <int V, typename R, typename AD = ad_identity>
+__device__ void a_fwd_level(cx<R>* w, const R* kt, int ltid, int T, int D, int H, int l, int min_hb = 0) {
     constexpr bool SW = variant_traits<V>::switches;
     const int n2 = 2 << D;
     cx<R> xa[KMAX], xb[KMAX];
@@ -125,10 +134,10 @@ __device__ void a_fwd_level(cx<R>* w, const R* kt, int ltid, int T, int D, int H
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid + k * T;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
-                xa[k] = w[it.base + it.i];
-                xb[k] = w[it.base + 2 * it.h - 1 - it.i];
+                xa[k] = w[AD::at(it.base + it.i)];
+                xb[k] = w[AD::at(it.base + 2 * it.h - 1 - it.i)];
             }
         }
     }
@@ -137,14 +146,14 @@ __device__ void a_fwd_level(cx<R>* w, const R* kt, int ltid, int T, int D, int H
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid + k * T;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
                 cx<R> lo, hi;
                 if (it.sigma == 0) { lo = xa[k] + xb[k]; hi = xa[k] - xb[k]; }
                 else { lo = xa[k] - xb[k]; hi = xa[k] + xb[k]; }
                 const R kk = (it.h == 1) ? cos_pi_4<R>() : kt[kidx(it.i, it.hb, D)];
-                w[it.base + it.i] = lo;
-                w[it.base + it.h + it.i] = hi * kk;
+                w[AD::at(it.base + it.i)] = lo;
+                w[AD::at(it.base + it.h + it.i)] = hi * kk;
             }
         }
     }
@@ -157,8 +166,8 @@ __device__ void a_fwd_level(cx<R>* w, const R* kt, int ltid, int T, int D, int H
 //   (DCT context; the DST context has the roles of even/odd array slots
 //   swapped because its harmonics start at k = 1).
 // ---------------------------------------------------------------------------
-template <int V, typename R>
-__device__ void a_bwd_level(cx<R>* w, int ltid, int T, int D, int H, int l) {
+template <int V, typename R, typename AD = ad_identity>
+__device__ void a_bwd_level(cx<R>* w, int ltid, int T, int D, int H, int l, int min_hb = 0) {
     constexpr bool SW = variant_traits<V>::switches;
     const int n2 = 2 << D;
     cx<R> lo[KMAX], f[KMAX], fn[KMAX];
@@ -166,17 +175,17 @@ __device__ void a_bwd_level(cx<R>* w, int ltid, int T, int D, int H, int l) {
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid + k * T;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
                 const int j = it.i, h = it.h;
-                lo[k] = w[it.base + j];
-                f[k] = w[it.base + h + j];
+                lo[k] = w[AD::at(it.base + j)];
+                f[k] = w[AD::at(it.base + h + j)];
                 // neighbour of the hi child's output used by M^F
                 bool up;  // true: f[j+1], false: f[j-1]
                 if (V == 4) up = (it.sigma == 0);
                 else up = (it.sigma != 0);  // V == 8
                 const int jn = up ? j + 1 : j - 1;
-                fn[k] = (jn >= 0 && jn < h) ? w[it.base + h + jn] : cx<R>{R(0), R(0)};
+                fn[k] = (jn >= 0 && jn < h) ? w[AD::at(it.base + h + jn)] : cx<R>{R(0), R(0)};
             }
         }
     }
@@ -185,7 +194,7 @@ __device__ void a_bwd_level(cx<R>* w, int ltid, int T, int D, int H, int l) {
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid + k * T;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
                 const int j = it.i;
                 cx<R> odd;  // value of the hi child's slot after M^F
@@ -193,11 +202,11 @@ __device__ void a_bwd_level(cx<R>* w, int ltid, int T, int D, int H, int l) {
                 else if (V == 4) odd = f[k] + fn[k];   // S(k) = E(k-1) + E(k+1)
                 else odd = (it.sigma == 0) ? f[k] - fn[k] : f[k] - fn[k];  // M8
                 if (it.sigma == 0) {
-                    w[it.base + 2 * j] = lo[k];
-                    w[it.base + 2 * j + 1] = odd;
+                    w[AD::at(it.base + 2 * j)] = lo[k];
+                    w[AD::at(it.base + 2 * j + 1)] = odd;
                 } else {
-                    w[it.base + 2 * j] = odd;
-                    w[it.base + 2 * j + 1] = lo[k];
+                    w[AD::at(it.base + 2 * j)] = odd;
+                    w[AD::at(it.base + 2 * j + 1)] = lo[k];
                 }
             }
         }
@@ -239,8 +248,8 @@ __device__ cx<R> chunk_carry(cx<R>* scr, int ltid, cx<R> total, bool participate
 //   M5 DCT: S(q-1) = E(q)/2, S(k-1) = E(k) + S(k+1) (descending)
 //   M5 DST: S(1) = E(0)/2, S(k+1) = E(k) + S(k-1) (ascending)
 // ---------------------------------------------------------------------------
-template <int V, typename R>
-__device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, int H, int l) {
+template <int V, typename R, typename AD = ad_identity>
+__device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, int H, int l, int min_hb = 0) {
     constexpr bool SW = variant_traits<V>::switches;
     constexpr R c = R(variant_traits<V>::sign);
     const int n2 = 2 << D;
@@ -251,10 +260,10 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
         const int t = ltid * KMAX + k;
         fwdk[k] = true;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
-                lo[k] = w[it.base + it.i];
-                a[k] = w[it.base + it.h + it.i];
+                lo[k] = w[AD::at(it.base + it.i)];
+                a[k] = w[AD::at(it.base + it.h + it.i)];
                 fwdk[k] = (V == 1) ? (it.sigma == 0) : (it.sigma != 0);
             }
         }
@@ -266,7 +275,7 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
         for (int k = 0; k < KMAX; ++k) {
             const int t = ltid * KMAX + k;
             if (t < n2) {
-                const item it = decode(t, D, l, H, SW);
+                const item it = decode(t, D, l, H, SW, min_hb);
                 if (it.active && it.h > 1 && fwdk[k]) {
                     cx<R> v = a[k];
                     if (it.i == 0) { Y = {R(0), R(0)}; v = v * R(0.5); }
@@ -280,7 +289,7 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
         for (int k = KMAX - 1; k >= 0; --k) {
             const int t = ltid * KMAX + k;
             if (t < n2) {
-                const item it = decode(t, D, l, H, SW);
+                const item it = decode(t, D, l, H, SW, min_hb);
                 if (it.active && it.h > 1 && !fwdk[k]) {
                     cx<R> v = a[k];
                     if (it.i == it.h - 1) { Y = {R(0), R(0)}; v = v * R(0.5); }
@@ -296,7 +305,7 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
     {
         const int t = ltid * KMAX;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             act0 = it.active;
             hseg = it.h;
         }
@@ -317,16 +326,16 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid * KMAX + k;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
                 const int j = it.i;
                 const cx<R> odd = (it.h == 1) ? a[k] : y[k];
                 if (it.sigma == 0) {
-                    w[it.base + 2 * j] = lo[k];
-                    w[it.base + 2 * j + 1] = odd;
+                    w[AD::at(it.base + 2 * j)] = lo[k];
+                    w[AD::at(it.base + 2 * j + 1)] = odd;
                 } else {
-                    w[it.base + 2 * j] = odd;
-                    w[it.base + 2 * j + 1] = lo[k];
+                    w[AD::at(it.base + 2 * j)] = odd;
+                    w[AD::at(it.base + 2 * j + 1)] = lo[k];
                 }
             }
         }
@@ -339,18 +348,18 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
 // tab:elabora_relations_B):
 //   dct[L]: S(k) = E(k) + O(k), S(L/2-k) = E(k) - O(k), S(q) = E(q)
 //   dst[L]: S(k) = O(k) + E(k), S(L/2-k) = O(k) - E(k), S(q) = O(q)
-// The DCT chain's top harmonic (k = L/2) lives in the extra slot w[H].
+// The DCT chain's top harmonic (k = L/2) lives in the extra slot w[AD::at(H)].
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ void a_chain(cx<R>* w, int ltid, int T, int D, int H) {
+template <typename R, typename AD = ad_identity>
+__device__ void a_chain(cx<R>* w, int ltid, int T, int D, int H, int jmax = 1 << 30, bool base = true) {
     // base dct[2]: (s0 + s1, s0 - s1) with s1 in the extra slot
-    if (ltid == 0) {
-        const cx<R> s0 = w[0], s1 = w[H];
-        w[0] = s0 + s1;
-        w[H] = s0 - s1;
+    if (base && ltid == 0) {
+        const cx<R> s0 = w[AD::at(0)], s1 = w[AD::at(H)];
+        w[AD::at(0)] = s0 + s1;
+        w[AD::at(H)] = s0 - s1;
     }
     __syncthreads();
-    for (int j = D; j >= 0; --j) {
+    for (int j = (jmax < D ? jmax : D); j >= 0; --j) {
         const int q = 1 << (D - j);
         cx<R> ra[KMAX], rb[KMAX], rx[KMAX];
 #pragma unroll
@@ -359,14 +368,14 @@ __device__ void a_chain(cx<R>* w, int ltid, int T, int D, int H) {
             if (t < 2 * q) {
                 const int side = t >= q, kk = t - side * q;
                 if (side == 0) {
-                    ra[k] = w[kk];       // E(k)
-                    rb[k] = w[q + kk];   // O(k)
-                    if (kk == 0) rx[k] = w[H];  // E(q)
+                    ra[k] = w[AD::at(kk)];       // E(k)
+                    rb[k] = w[AD::at(q + kk)];   // O(k)
+                    if (kk == 0) rx[k] = w[AD::at(H)];  // E(q)
                 } else if (kk > 0) {
-                    ra[k] = w[H + kk];           // E(k)
-                    rb[k] = w[H + q + kk - 1];   // O(k)
+                    ra[k] = w[AD::at(H + kk)];           // E(k)
+                    rb[k] = w[AD::at(H + q + kk - 1)];   // O(k)
                 } else {
-                    rb[k] = w[H + 2 * q - 1];    // O(q)
+                    rb[k] = w[AD::at(H + 2 * q - 1)];    // O(q)
                 }
             }
         }
@@ -377,18 +386,18 @@ __device__ void a_chain(cx<R>* w, int ltid, int T, int D, int H) {
             if (t < 2 * q) {
                 const int side = t >= q, kk = t - side * q;
                 if (side == 0) {
-                    w[kk] = ra[k] + rb[k];
+                    w[AD::at(kk)] = ra[k] + rb[k];
                     if (kk > 0) {
-                        w[2 * q - kk] = ra[k] - rb[k];
+                        w[AD::at(2 * q - kk)] = ra[k] - rb[k];
                     } else {
-                        w[H] = ra[k] - rb[k];  // S(L/2)
-                        w[q] = rx[k];          // S(q) = E(q)
+                        w[AD::at(H)] = ra[k] - rb[k];  // S(L/2)
+                        w[AD::at(q)] = rx[k];          // S(q) = E(q)
                     }
                 } else if (kk > 0) {
-                    w[H + kk] = rb[k] + ra[k];
-                    w[H + 2 * q - kk] = rb[k] - ra[k];
+                    w[AD::at(H + kk)] = rb[k] + ra[k];
+                    w[AD::at(H + 2 * q - kk)] = rb[k] - ra[k];
                 } else {
-                    w[H + q] = rb[k];
+                    w[AD::at(H + q)] = rb[k];
                 }
             }
         }
@@ -402,9 +411,9 @@ __device__ void a_chain(cx<R>* w, int ltid, int T, int D, int H) {
 //   dst[L]: e(n) = s(n) - s(L/2-n), o(n) = s(n) + s(L/2-n), o(q) = s(q)
 // e stays in place as the next chain signal, o goes to block j.
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ void b_chain_fwd(cx<R>* w, int ltid, int T, int D, int H) {
-    for (int j = 0; j <= D; ++j) {
+template <typename R, typename AD = ad_identity>
+__device__ void b_chain_fwd(cx<R>* w, int ltid, int T, int D, int H, int jmax = 1 << 30) {
+    for (int j = 0; j <= (jmax < D ? jmax : D); ++j) {
         const int q = 1 << (D - j);
         cx<R> ra[KMAX], rb[KMAX], rm[KMAX];
 #pragma unroll
@@ -413,14 +422,14 @@ __device__ void b_chain_fwd(cx<R>* w, int ltid, int T, int D, int H) {
             if (t < 2 * q) {
                 const int side = t >= q, n = t - side * q;
                 if (side == 0) {
-                    ra[k] = w[n];
-                    rb[k] = (n == 0) ? w[H] : w[2 * q - n];
-                    if (n == 0) rm[k] = w[q];
+                    ra[k] = w[AD::at(n)];
+                    rb[k] = (n == 0) ? w[AD::at(H)] : w[AD::at(2 * q - n)];
+                    if (n == 0) rm[k] = w[AD::at(q)];
                 } else if (n > 0) {
-                    ra[k] = w[H + n];
-                    rb[k] = w[H + 2 * q - n];
+                    ra[k] = w[AD::at(H + n)];
+                    rb[k] = w[AD::at(H + 2 * q - n)];
                 } else {
-                    rm[k] = w[H + q];
+                    rm[k] = w[AD::at(H + q)];
                 }
             }
         }
@@ -431,14 +440,14 @@ __device__ void b_chain_fwd(cx<R>* w, int ltid, int T, int D, int H) {
             if (t < 2 * q) {
                 const int side = t >= q, n = t - side * q;
                 if (side == 0) {
-                    w[n] = ra[k] + rb[k];
-                    w[q + n] = ra[k] - rb[k];
-                    if (n == 0) w[H] = rm[k];
+                    w[AD::at(n)] = ra[k] + rb[k];
+                    w[AD::at(q + n)] = ra[k] - rb[k];
+                    if (n == 0) w[AD::at(H)] = rm[k];
                 } else if (n > 0) {
-                    w[H + n] = ra[k] - rb[k];
-                    w[H + q + n - 1] = ra[k] + rb[k];
+                    w[AD::at(H + n)] = ra[k] - rb[k];
+                    w[AD::at(H + q + n - 1)] = ra[k] + rb[k];
                 } else {
-                    w[H + 2 * q - 1] = rm[k];
+                    w[AD::at(H + 2 * q - 1)] = rm[k];
                 }
             }
         }
@@ -450,15 +459,15 @@ __device__ void b_chain_fwd(cx<R>* w, int ltid, int T, int D, int H) {
 // Skeleton B, backward phase of the chain: the harmonics are re-interleaved
 // (even k from dct[L/2], odd k from dct_to[L]); the dct[2] base first.
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ void b_chain_bwd(cx<R>* w, int ltid, int T, int D, int H) {
-    if (ltid == 0) {
-        const cx<R> s0 = w[0], s1 = w[H];
-        w[0] = s0 + s1;
-        w[H] = s0 - s1;
+template <typename R, typename AD = ad_identity>
+__device__ void b_chain_bwd(cx<R>* w, int ltid, int T, int D, int H, int jmax = 1 << 30, bool base = true) {
+    if (base && ltid == 0) {
+        const cx<R> s0 = w[AD::at(0)], s1 = w[AD::at(H)];
+        w[AD::at(0)] = s0 + s1;
+        w[AD::at(H)] = s0 - s1;
     }
     __syncthreads();
-    for (int j = D; j >= 0; --j) {
+    for (int j = (jmax < D ? jmax : D); j >= 0; --j) {
         const int q = 1 << (D - j);
         cx<R> re[KMAX], ro[KMAX];
 #pragma unroll
@@ -467,8 +476,8 @@ __device__ void b_chain_bwd(cx<R>* w, int ltid, int T, int D, int H) {
             if (t < 2 * q) {
                 const int side = t >= q, i = t - side * q;
                 const int off = side * H;
-                if (side == 0 || i > 0) re[k] = w[off + i];
-                ro[k] = w[off + q + i];
+                if (side == 0 || i > 0) re[k] = w[AD::at(off + i)];
+                ro[k] = w[AD::at(off + q + i)];
             }
         }
         __syncthreads();
@@ -478,8 +487,8 @@ __device__ void b_chain_bwd(cx<R>* w, int ltid, int T, int D, int H) {
             if (t < 2 * q) {
                 const int side = t >= q, i = t - side * q;
                 const int off = side * H;
-                if (side == 0 || i > 0) w[off + 2 * i] = re[k];
-                w[off + 2 * i + 1] = ro[k];
+                if (side == 0 || i > 0) w[AD::at(off + 2 * i)] = re[k];
+                w[AD::at(off + 2 * i + 1)] = ro[k];
             }
         }
         __syncthreads();
@@ -492,8 +501,8 @@ __device__ void b_chain_bwd(cx<R>* w, int ltid, int T, int D, int H) {
 //   then M^T on the odd part: neighbour sums (M2) or differences (M6);
 //   L = 8 base: o * cos(pi/4).
 // ---------------------------------------------------------------------------
-template <int V, typename R>
-__device__ void b_fwd_level(cx<R>* w, int ltid, int T, int D, int H, int l) {
+template <int V, typename R, typename AD = ad_identity>
+__device__ void b_fwd_level(cx<R>* w, int ltid, int T, int D, int H, int l, int min_hb = 0) {
     constexpr bool SW = variant_traits<V>::switches;
     const int n2 = 2 << D;
     cx<R> lo[KMAX], xo[KMAX], xn[KMAX];
@@ -501,19 +510,19 @@ __device__ void b_fwd_level(cx<R>* w, int ltid, int T, int D, int H, int l) {
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid + k * T;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
                 const int i = it.i, h = it.h;
                 const bool dctc = (it.sigma == 0);
                 // DCT context: n = 2i even -> slot 2i, odd -> slot 2i+1;
                 // DST context (n starts at 1): even n -> slot 2i+1, odd -> 2i
-                lo[k] = w[it.base + (dctc ? 2 * i : 2 * i + 1)];
-                xo[k] = w[it.base + (dctc ? 2 * i + 1 : 2 * i)];
+                lo[k] = w[AD::at(it.base + (dctc ? 2 * i : 2 * i + 1))];
+                xo[k] = w[AD::at(it.base + (dctc ? 2 * i + 1 : 2 * i))];
                 bool up;  // neighbour o[i+1] (true) or o[i-1]
                 if (V == 2) up = !dctc;
                 else up = dctc;  // V == 6
                 const int in = up ? i + 1 : i - 1;
-                xn[k] = (in >= 0 && in < h) ? w[it.base + (dctc ? 2 * in + 1 : 2 * in)] : cx<R>{R(0), R(0)};
+                xn[k] = (in >= 0 && in < h) ? w[AD::at(it.base + (dctc ? 2 * in + 1 : 2 * in))] : cx<R>{R(0), R(0)};
             }
         }
     }
@@ -522,14 +531,14 @@ __device__ void b_fwd_level(cx<R>* w, int ltid, int T, int D, int H, int l) {
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid + k * T;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
                 cx<R> hi;
                 if (it.h == 1) hi = xo[k] * cos_pi_4<R>();
                 else if (V == 2) hi = xo[k] + xn[k];   // o(n-1) + o(n+1)
                 else hi = xo[k] - xn[k];               // M6: differences
-                w[it.base + it.i] = lo[k];
-                w[it.base + it.h + it.i] = hi;
+                w[AD::at(it.base + it.i)] = lo[k];
+                w[AD::at(it.base + it.h + it.i)] = hi;
             }
         }
     }
@@ -544,8 +553,8 @@ __device__ void b_fwd_level(cx<R>* w, int ltid, int T, int D, int H, int l) {
 //   M7 DCT: e(2) = s(1), e(n) = s(n-1) + e(n-2) asc., e(q) = [s(q-1) + e(q-2)]/2
 //   M7 DST: e(q-2) = s(q-1), e(n) = s(n+1) + e(n+2) desc., e(0) = [s(1) + e(2)]/2
 // ---------------------------------------------------------------------------
-template <int V, typename R>
-__device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, int H, int l) {
+template <int V, typename R, typename AD = ad_identity>
+__device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, int H, int l, int min_hb = 0) {
     constexpr bool SW = variant_traits<V>::switches;
     constexpr R c = R(variant_traits<V>::sign);
     const int n2 = 2 << D;
@@ -556,11 +565,11 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
         const int t = ltid * KMAX + k;
         fwdk[k] = true;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
                 const bool dctc = (it.sigma == 0);
-                lo[k] = w[it.base + (dctc ? 2 * it.i : 2 * it.i + 1)];
-                a[k] = w[it.base + (dctc ? 2 * it.i + 1 : 2 * it.i)];
+                lo[k] = w[AD::at(it.base + (dctc ? 2 * it.i : 2 * it.i + 1))];
+                a[k] = w[AD::at(it.base + (dctc ? 2 * it.i + 1 : 2 * it.i))];
                 fwdk[k] = (V == 3) ? !dctc : dctc;
             }
         }
@@ -571,7 +580,7 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
         for (int k = 0; k < KMAX; ++k) {
             const int t = ltid * KMAX + k;
             if (t < n2) {
-                const item it = decode(t, D, l, H, SW);
+                const item it = decode(t, D, l, H, SW, min_hb);
                 if (it.active && it.h > 1 && fwdk[k]) {
                     if (it.i == 0) Y = {R(0), R(0)};
                     Y = a[k] + Y * c;
@@ -584,7 +593,7 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
         for (int k = KMAX - 1; k >= 0; --k) {
             const int t = ltid * KMAX + k;
             if (t < n2) {
-                const item it = decode(t, D, l, H, SW);
+                const item it = decode(t, D, l, H, SW, min_hb);
                 if (it.active && it.h > 1 && !fwdk[k]) {
                     if (it.i == it.h - 1) Y = {R(0), R(0)};
                     Y = a[k] + Y * c;
@@ -598,7 +607,7 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
     {
         const int t = ltid * KMAX;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             act0 = it.active;
             hseg = it.h;
         }
@@ -619,7 +628,7 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid * KMAX + k;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
                 cx<R> hi;
                 if (it.h == 1) {
@@ -629,8 +638,8 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
                     const bool last = fwdk[k] ? (it.i == it.h - 1) : (it.i == 0);
                     if (last) hi = hi * R(0.5);
                 }
-                w[it.base + it.i] = lo[k];
-                w[it.base + it.h + it.i] = hi;
+                w[AD::at(it.base + it.i)] = lo[k];
+                w[AD::at(it.base + it.h + it.i)] = hi;
             }
         }
     }
@@ -642,8 +651,8 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
 //   M^F (M2, M3, M6, M7): O = F times 1/(2cos), 2cos, 1/(2sin), 2sin of theta*k
 //   D_n^F: DCT S(k) = E + O, S(L/2-k) = E - O; DST S(k) = O + E, S(L/2-k) = O - E
 // ---------------------------------------------------------------------------
-template <int V, typename R>
-__device__ void b_bwd_level(cx<R>* w, const R* kt, int ltid, int T, int D, int H, int l) {
+template <int V, typename R, typename AD = ad_identity>
+__device__ void b_bwd_level(cx<R>* w, const R* kt, int ltid, int T, int D, int H, int l, int min_hb = 0) {
     constexpr bool SW = variant_traits<V>::switches;
     const int n2 = 2 << D;
     cx<R> e[KMAX], f[KMAX];
@@ -651,10 +660,10 @@ __device__ void b_bwd_level(cx<R>* w, const R* kt, int ltid, int T, int D, int H
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid + k * T;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
-                e[k] = w[it.base + it.i];
-                f[k] = w[it.base + it.h + it.i];
+                e[k] = w[AD::at(it.base + it.i)];
+                f[k] = w[AD::at(it.base + it.h + it.i)];
             }
         }
     }
@@ -663,16 +672,16 @@ __device__ void b_bwd_level(cx<R>* w, const R* kt, int ltid, int T, int D, int H
     for (int k = 0; k < KMAX; ++k) {
         const int t = ltid + k * T;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW);
+            const item it = decode(t, D, l, H, SW, min_hb);
             if (it.active) {
                 const cx<R> O = (it.h == 1) ? f[k] : f[k] * kt[kidx(it.i, it.hb, D)];
                 const int s1 = 2 * it.h - 1 - it.i;
                 if (it.sigma == 0) {
-                    w[it.base + it.i] = e[k] + O;
-                    w[it.base + s1] = e[k] - O;
+                    w[AD::at(it.base + it.i)] = e[k] + O;
+                    w[AD::at(it.base + s1)] = e[k] - O;
                 } else {
-                    w[it.base + it.i] = O + e[k];
-                    w[it.base + s1] = O - e[k];
+                    w[AD::at(it.base + it.i)] = O + e[k];
+                    w[AD::at(it.base + s1)] = O - e[k];
                 }
             }
         }
@@ -701,24 +710,24 @@ __device__ void load_constants(R* kt, const R* ktab, int Q, int kshift, bool ont
 }
 
 // the recursion of both sides between the D_r split and the D_c combine
-template <int V, typename R>
+template <int V, typename R, typename AD = ad_identity>
 __device__ void core(cx<R>* w, const R* kt, cx<R>* scr, int ltid, int T, int D, int H) {
     using VT = variant_traits<V>;
     if constexpr (VT::skel_a) {
-        for (int l = 0; l < D; ++l) a_fwd_level<V, R>(w, kt, ltid, T, D, H, l);
+        for (int l = 0; l < D; ++l) a_fwd_level<V, R, AD>(w, kt, ltid, T, D, H, l);
         for (int l = D - 1; l >= 0; --l) {
-            if constexpr (VT::recurrence) a_bwd_scan_level<V, R>(w, scr, ltid, T, D, H, l);
-            else a_bwd_level<V, R>(w, ltid, T, D, H, l);
+            if constexpr (VT::recurrence) a_bwd_scan_level<V, R, AD>(w, scr, ltid, T, D, H, l);
+            else a_bwd_level<V, R, AD>(w, ltid, T, D, H, l);
         }
-        a_chain<R>(w, ltid, T, D, H);
+        a_chain<R, AD>(w, ltid, T, D, H);
     } else {
-        b_chain_fwd<R>(w, ltid, T, D, H);
+        b_chain_fwd<R, AD>(w, ltid, T, D, H);
         for (int l = 0; l < D; ++l) {
-            if constexpr (VT::recurrence) b_fwd_scan_level<V, R>(w, scr, ltid, T, D, H, l);
-            else b_fwd_level<V, R>(w, ltid, T, D, H, l);
+            if constexpr (VT::recurrence) b_fwd_scan_level<V, R, AD>(w, scr, ltid, T, D, H, l);
+            else b_fwd_level<V, R, AD>(w, ltid, T, D, H, l);
         }
-        for (int l = D - 1; l >= 0; --l) b_bwd_level<V, R>(w, kt, ltid, T, D, H, l);
-        b_chain_bwd<R>(w, ltid, T, D, H);
+        for (int l = D - 1; l >= 0; --l) b_bwd_level<V, R, AD>(w, kt, ltid, T, D, H, l);
+        b_chain_bwd<R, AD>(w, ltid, T, D, H);
     }
 }
 
