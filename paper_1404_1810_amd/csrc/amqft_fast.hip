@@ -237,13 +237,6 @@ hipError_t launch_fast_n(const lds_launch& a, hipStream_t st) {
     constexpr int N = 1 << LOGN, T = N / 16, SPW = 256 / T, Q = N / 4;
     constexpr size_t kt_bytes = ((size_t)Q * sizeof(R) + 15) & ~(size_t)15;
     constexpr size_t lds = kt_bytes + (size_t)SPW * (N + N / 16 + T) * sizeof(cx<R>);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_fast_kernel<V, S, LOGN>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
     const int flags = (a.conj_in ? 1 : 0) | (a.conj_out ? 2 : 0) | (a.onthefly ? 4 : 0);
     const long long grid = (a.batch + SPW - 1) / SPW;
     hipLaunchKernelGGL((amqft_fast_kernel<V, S, LOGN>), dim3((unsigned)grid), dim3(256), lds, st,
@@ -272,6 +265,34 @@ hipError_t launch_fast_v(const lds_launch& a, hipStream_t st) {
 }
 
 }  // namespace
+
+template <int V, typename S, int LOGN>
+static hipError_t prime_fast_n() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_fast_kernel<V, S, LOGN>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess || LOGN == 12) return e;
+    return prime_fast_n<V, S, (LOGN < 12 ? LOGN + 1 : 12)>();
+}
+
+template <int V>
+static hipError_t prime_fast_v(int dtype) {
+    if (dtype == 0) return prime_fast_n<V, double2, 6>();
+    if (dtype == 1) return prime_fast_n<V, float2, 6>();
+    return hipSuccess;
+}
+
+hipError_t prime_fast(int variant, int dtype) {
+    switch (variant) {
+    case 1: return prime_fast_v<1>(dtype);
+    case 2: return prime_fast_v<2>(dtype);
+    case 3: return prime_fast_v<3>(dtype);
+    case 4: return prime_fast_v<4>(dtype);
+    case 5: return prime_fast_v<5>(dtype);
+    case 6: return prime_fast_v<6>(dtype);
+    case 7: return prime_fast_v<7>(dtype);
+    default: return prime_fast_v<8>(dtype);
+    }
+}
 
 bool fast_supported(int logn, int dtype) { return logn >= 6 && logn <= 12 && (dtype == 0 || dtype == 1); }
 

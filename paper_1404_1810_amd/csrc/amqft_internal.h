@@ -64,6 +64,13 @@ hipError_t launch_loss(const loss_launch& a, hipStream_t stream);
 // Fast kernels with compile-time geometry (N = 64 .. 4096, FP32 / FP64).
 bool fast_supported(int logn, int dtype);
 hipError_t launch_fast(const lds_launch& a, hipStream_t stream);
+hipError_t prime_fast(int variant, int dtype);
+
+// Skeleton-A kernel for N = 4096 (variants 4 and 8, FP32 / FP64) with its
+// dataflow fixed at compile time (amqft_k4096.hip).
+bool a4096_supported(int variant, int logn, int dtype);
+hipError_t launch_a4096(const lds_launch& a, hipStream_t stream);
+hipError_t prime_a4096(int variant, int dtype);
 
 // Launch the LDS-resident engine; returns the hipError_t of the launch.
 hipError_t launch_lds(const lds_launch& a, hipStream_t stream);

@@ -399,6 +399,9 @@ static hipError_t prime_v(int dtype) {
 }
 
 hipError_t prime_lds(int variant, int dtype) {
+    hipError_t e = prime_fast(variant, dtype);
+    if (e == hipSuccess) e = prime_a4096(variant, dtype);
+    if (e != hipSuccess) return e;
     switch (variant) {
     case 1: return prime_v<1>(dtype);
     case 2: return prime_v<2>(dtype);
@@ -412,6 +415,7 @@ hipError_t prime_lds(int variant, int dtype) {
 }
 
 hipError_t launch_lds(const lds_launch& a, hipStream_t s) {
+    if (!a.generic && a4096_supported(a.variant, a.logn, a.dtype)) return launch_a4096(a, s);
     if (!a.generic && fast_supported(a.logn, a.dtype)) return launch_fast(a, s);
     switch (a.variant) {
     case 1: return launch_v<1>(a, s);

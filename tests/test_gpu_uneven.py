@@ -47,7 +47,7 @@ def test_uneven_against_oracle(variant):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("variant", [2, 4])
-def test_uneven_equals_plain_per_length(variant):
+def test_uneven_matches_plain_per_length(variant):
     from paper_1404_1810_amd import api
     lengths, offsets = inputs.uneven_lengths(count=300, seed=7)
     total = int(offsets[-1])
@@ -65,7 +65,14 @@ def test_uneven_equals_plain_per_length(variant):
         for r, i in enumerate(idx):
             ref[offsets[i]:offsets[i] + k] = out[r]
     torch.cuda.synchronize()
-    assert torch.equal(y, ref)
+    # the persistent kernel and the per-length kernels schedule the same
+    # relations differently (different rounding order): compare per length
+    yn, rn = y.cpu().numpy(), ref.cpu().numpy()
+    for k in np.unique(lengths):
+        idx = np.nonzero(lengths == k)[0]
+        a = np.concatenate([yn[offsets[i]:offsets[i] + k] for i in idx])
+        b = np.concatenate([rn[offsets[i]:offsets[i] + k] for i in idx])
+        assert rel(a, b) < 1e-5, (k, rel(a, b))
 
 
 @pytest.mark.gpu
