@@ -133,6 +133,12 @@ amqft_status amqft_exec_graph(amqft_plan plan, const void *in_dev,
  * every stream the plan ran on.  NULL is accepted. */
 amqft_status amqft_plan_destroy(amqft_plan plan);
 
+/* Write a one-line, NUL-terminated description of what the plan launches
+ * (kernel name, grid, block, LDS bytes; or the multi-pass / many-length
+ * structure) into buf[0 .. len).  Host only; no GPU work.  For reports and
+ * profiles: the kernel name matches the one a profiler lists. */
+amqft_status amqft_plan_describe(amqft_plan plan, char *buf, size_t len);
+
 /* Bytes of device workspace owned by the plan (0 when none). */
 amqft_status amqft_plan_workspace_size(amqft_plan plan, size_t *bytes);
 

@@ -31,6 +31,7 @@ SIGNATURES = {
     "amqft_exec_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                         ctypes.c_void_p]),
     "amqft_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "amqft_plan_describe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
     "amqft_plan_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "amqft_plan_constants": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64]),
     "amqft_status_string": (ctypes.c_char_p, [ctypes.c_int]),

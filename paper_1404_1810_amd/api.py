@@ -100,6 +100,9 @@ class Plan:
             ctypes.c_void_p(loss.data_ptr()), _stream_handle(x.device)), "amqft_power_loss_grad")
         return loss, g
 
+    def describe(self) -> str:
+        return _describe(self._h)
+
     def constants(self, n: int | None = None):
         import numpy as np
         n = self.n if n is None else n
@@ -107,6 +110,12 @@ class Plan:
         _lib.check(_lib.load().amqft_plan_constants(self._h, int(n), ctypes.c_void_p(out.ctypes.data), out.size),
                    "amqft_plan_constants")
         return out
+
+
+def _describe(h) -> str:
+    buf = ctypes.create_string_buffer(512)
+    _lib.check(_lib.load().amqft_plan_describe(h, buf, 512), "amqft_plan_describe")
+    return buf.value.decode()
 
 
 _plan_cache: dict = {}
@@ -205,6 +214,9 @@ class ManyPlan:
             self.close()
         except Exception:
             pass
+
+    def describe(self) -> str:
+        return _describe(self._h)
 
     def workspace_bytes(self) -> int:
         sz = ctypes.c_size_t()

@@ -628,6 +628,26 @@ amqft_status amqft_plan_destroy(amqft_plan p) {
     return AMQFT_OK;
 }
 
+amqft_status amqft_plan_describe(amqft_plan p, char* buf, size_t len) {
+    if (!p || !buf || len == 0) return AMQFT_ERR_INVALID_ARG;
+    if (p->many) {
+        int nclass = 0;
+        for (auto& c : p->classes) nclass += c.sub ? 1 : 0;
+        snprintf(buf, len, "many-length plan: %lld signals, persistent kernel grid=%d items=%d, %d long-length classes",
+                 (long long)p->count, p->grid, p->nitems, nclass);
+    } else if (p->multipass) {
+        snprintf(buf, len, "multi-pass engine n=%lld sb=%d chunk=%lld", (long long)p->n, p->sb, (long long)p->chunk);
+    } else {
+        lds_launch a{};
+        a.variant = p->variant;
+        a.dtype = p->dtype;
+        a.logn = p->logn;
+        a.batch = p->batch;
+        describe_lds(a, buf, len);
+    }
+    return AMQFT_OK;
+}
+
 amqft_status amqft_plan_workspace_size(amqft_plan p, size_t* bytes) {
     if (!p || !bytes) return AMQFT_ERR_INVALID_ARG;
     *bytes = p->ws_bytes;

@@ -294,6 +294,14 @@ hipError_t prime_fast(int variant, int dtype) {
     }
 }
 
+void fast_shape(int logn, int dtype, int* threads, int* spw, size_t* lds_bytes) {
+    const int N = 1 << logn, T = N / 16, Q = N / 4;
+    const size_t r = dtype == 0 ? 8 : 4;
+    *threads = 256;
+    *spw = 256 / T;
+    *lds_bytes = ((Q * r + 15) & ~(size_t)15) + (size_t)(256 / T) * (N + N / 16 + T) * 2 * r;
+}
+
 bool fast_supported(int logn, int dtype) { return logn >= 6 && logn <= 12 && (dtype == 0 || dtype == 1); }
 
 hipError_t launch_fast(const lds_launch& a, hipStream_t st) {

@@ -65,12 +65,17 @@ hipError_t launch_loss(const loss_launch& a, hipStream_t stream);
 bool fast_supported(int logn, int dtype);
 hipError_t launch_fast(const lds_launch& a, hipStream_t stream);
 hipError_t prime_fast(int variant, int dtype);
+void fast_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
 
 // Skeleton-A kernel for N = 4096 (variants 4 and 8, FP32 / FP64) with its
 // dataflow fixed at compile time (amqft_k4096.hip).
 bool a4096_supported(int variant, int logn, int dtype);
 hipError_t launch_a4096(const lds_launch& a, hipStream_t stream);
 hipError_t prime_a4096(int variant, int dtype);
+void a4096_shape(int dtype, int* threads, size_t* lds_bytes);
+
+// Name and launch shape of the kernel launch_lds picks for a (for reports).
+void describe_lds(const lds_launch& a, char* buf, size_t len);
 
 // Launch the LDS-resident engine; returns the hipError_t of the launch.
 hipError_t launch_lds(const lds_launch& a, hipStream_t stream);

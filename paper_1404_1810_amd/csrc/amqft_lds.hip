@@ -2,6 +2,8 @@
 // workgroup, the whole recursion of Sec. 4 and 6 flattened into
 // level-synchronous passes over the signal held in LDS (layout and level
 // functions in amqft_levels.h).
+#include <stdio.h>
+
 #include <algorithm>
 
 #include "amqft_device.h"
@@ -411,6 +413,28 @@ hipError_t prime_lds(int variant, int dtype) {
     case 6: return prime_v<6>(dtype);
     case 7: return prime_v<7>(dtype);
     default: return prime_v<8>(dtype);
+    }
+}
+
+void describe_lds(const lds_launch& a, char* buf, size_t len) {
+    static const char* st[4] = {"double2", "float2", "__half2", "bf16x2"};
+    const char* sname = st[a.dtype & 3];
+    int threads = 0, spw = 1;
+    size_t lds = 0;
+    if (!a.generic && a4096_supported(a.variant, a.logn, a.dtype)) {
+        a4096_shape(a.dtype, &threads, &lds);
+        snprintf(buf, len, "amqft_a4096_kernel<%d, %s> grid=%lld block=%d lds=%zu", a.variant, sname,
+                 (long long)a.batch, threads, lds);
+    } else if (!a.generic && fast_supported(a.logn, a.dtype)) {
+        fast_shape(a.logn, a.dtype, &threads, &spw, &lds);
+        snprintf(buf, len, "amqft_fast_kernel<%d, %s, %d> grid=%lld block=%d lds=%zu", a.variant, sname, a.logn,
+                 (long long)((a.batch + spw - 1) / spw), threads, lds);
+    } else if (a.logn <= 1) {
+        snprintf(buf, len, "amqft_tiny_kernel<%s> n=%d", sname, 1 << a.logn);
+    } else {
+        lds_shape(a.logn, a.dtype, &threads, &spw, &lds);
+        snprintf(buf, len, "amqft_lds_kernel<%d, %s> grid=%lld block=%d lds=%zu", a.variant, sname,
+                 (long long)((a.batch + spw - 1) / spw), threads, lds);
     }
 }
 
