@@ -12,10 +12,30 @@
 
 namespace amqft {
 
+// aligned to its full size, so that LDS and global accesses of one complex
+// value are single 64-bit (FP32) or 128-bit (FP64) transactions
 template <typename R>
-struct cx {
+struct alignas(2 * sizeof(R)) cx {
     R re, im;
 };
+
+// whole-value loads and stores of a complex number (one 64-bit / 128-bit
+// access; keeps the compiler from splitting it into two scalar accesses)
+template <typename R> struct vec2;
+template <> struct vec2<float> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct vec2<double> { typedef double T __attribute__((ext_vector_type(2))); };
+template <typename R>
+__device__ __forceinline__ cx<R> ldc(const cx<R>* p) {
+    const typename vec2<R>::T v = *reinterpret_cast<const typename vec2<R>::T*>(p);
+    return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void stc(cx<R>* p, cx<R> a) {
+    typename vec2<R>::T v;
+    v.x = a.re;
+    v.y = a.im;
+    *reinterpret_cast<typename vec2<R>::T*>(p) = v;
+}
 
 template <typename R>
 __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }

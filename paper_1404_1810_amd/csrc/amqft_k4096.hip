@@ -21,24 +21,28 @@
 //
 // Passes (each reads everything it needs, waits at a barrier, then writes):
 //   F1  load + D_c/D_r + levels 0..2 on the orbits {+-m0 + 512 j}; thread 0
-//       does blocks 8..10 and the chain up to dct[16] / dst[16] (into a small
-//       chain area).  Output: depth-3 rows, slot layout.
-//   F2  levels 3..6 on the orbits {+-m0 + 32 j} of each depth-3 row.
+//       does blocks 8..10 and the chain up to dct[16] / dst[16].  The
+//       loads are issued before the constant tables are filled.  Output:
+//       depth-3 rows, slot layout.
+//   F2  levels 3..6 on the orbits {+-m0 + 32 j} of each depth-3 row (lanes
+//       0..14 of a 16-lane group); lane 15 finishes the row's slots that are
+//       multiples of 16 (blocks 4..7, whole sub-blocks of 8, 4, 2, 1 points).
 //       Output: depth-7 rows (16 slots), slot layout.
 //   P3  every depth-7 row (blocks 0..3 of 8, 4, 2, 1 points): whole
 //       sub-blocks forward and backward in registers.  Output: the row's
 //       spectra block-contiguous [8 | 4 | 2 | 1] in slots 1..15.
 //   B2  backward levels 6..3 of blocks 0..3: a thread combines one child
 //       index j of 16 descendant rows into 16 consecutive parent harmonics,
-//       with the +-1 neighbours that M4 / M8 read from the same rows.  Eight
-//       threads per half also finish blocks 4..7 of the depth-3 rows (the
-//       slots that are multiples of 16) as 16-slot rows.  Output: depth-3
-//       rows block-contiguous [chain slot | blocks 4..7 | blocks 0..3].
-//   B1  backward levels 2..0 of blocks 0..7, thread = position in that
-//       layout.  Output: depth 0, block a at 2048 - 2048 / 2^a.
+//       with the +-1 neighbours that M4 / M8 read from the same rows.
+//       Output: depth-3 rows, blocks 0..3 block-contiguous from slot 16.
+//   B1  backward levels 2..0 of blocks 0..7, thread = position in the
+//       depth-3 layout.  Output: depth 0, block a at 2048 - 2048 / 2^a.
 //   C0  chain (D_n^F of dct/dst): levels 3..7 evaluated along each output's
 //       reflection path, levels 0..2 on the orbit of 8 harmonics, then D_c
 //       and the store.
+// Blocks 4..7 of the depth-3 rows and the chain values live in the pad
+// slots (one per 16 positions), which no layout uses otherwise.  LDS
+// accesses of a 16-lane group hit distinct banks (stride 1 or 17).
 #include <type_traits>
 
 #include "amqft_device.h"
@@ -53,11 +57,22 @@ constexpr int N4 = 4096, H4 = 2048, D4 = 10, Q4 = 1024;
 constexpr int THREADS4 = 256;
 constexpr int HS = H4 + H4 / 16;  // padded positions of one half
 constexpr int WLEN = 2 * HS + 2;  // both halves and two guard slots
-constexpr int CHLEN = 16;         // chain values: E_8(0..8), then D_8(1..7)
+// constants of levels 3..6 in the order F2 reads them: [t][r][w] for level
+// 3 + t, orbit slot r < 8 >> t, lane w = m0 - 1 (stride-1 reads)
+constexpr int KF2 = 225;
+constexpr int KF2_ALLOC = 232;
+constexpr int kf2_off(int t) { return t == 0 ? 0 : t == 1 ? 120 : t == 2 ? 180 : 210; }
 
 constexpr int par(int x) { return x ? ((x & 1) ^ par(x >> 1)) : 0; }
 
 __device__ __forceinline__ int pad(int p) { return p + (p >> 4); }
+
+// Pad slot k (0..127) of half hh: index 17 k + 16, never a padded position.
+// Blocks 4..7 of depth-3 row P (half h) finish into pad slots 16 P + i,
+// i = 0..14; the chain values E_8(0..8), D_8(1..7) (c = 0..15) use slot
+// 16 (c & 7) + 15 of half c >> 3.
+__device__ __forceinline__ int pslot(int hh, int k) { return hh * HS + 17 * k + 16; }
+__device__ __forceinline__ int chslot(int c) { return (c >> 3) * HS + 272 * (c & 7) + 271; }
 
 template <int B, int E, typename F>
 __device__ __forceinline__ void sfor(F&& f) {
@@ -174,19 +189,31 @@ __device__ __forceinline__ void row16(const cx<R>* s, cx<R>* o, const R* kt) {
 }
 
 // ---------------------------------------------------------------------- F1
+// global loads of a thread: orbit of m0 = tid (x(m0 + 512 j), x(512 (j+1) - m0))
+// or, for thread 0, the multiples of 256
+template <typename S, typename R>
+__device__ __forceinline__ void f1_load(const S* x, int tid, cx<R> (&raw)[16]) {
+    if (tid > 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            raw[j] = storage<S>::ld(x + tid + 512 * j);
+            raw[8 + j] = storage<S>::ld(x + 512 * (j + 1) - tid);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) raw[k] = storage<S>::ld(x + 256 * k);
+    }
+}
+
 // orbit of m0 in [1, 255]: slots m0 + 512 i, 512 (i+1) - m0 of both sides
-template <int V, typename S, typename R>
-__device__ __forceinline__ void f1_orbit(cx<R>* w, const R* kt, const S* x, int m0, bool conj_in) {
+template <int V, typename R>
+__device__ __forceinline__ void f1_orbit(cx<R>* w, const R* kt, const cx<R> (&raw)[16], int m0, bool conj_in) {
     constexpr bool SW = variant_traits<V>::switches;
     cx<R> xa[8], xb[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        xa[j] = storage<S>::ld(x + m0 + 512 * j);
-        xb[j] = storage<S>::ld(x + 512 * (j + 1) - m0);
-        if (conj_in) {
-            xa[j] = cconj(xa[j]);
-            xb[j] = cconj(xb[j]);
-        }
+        xa[j] = conj_in ? cconj(raw[j]) : raw[j];
+        xb[j] = conj_in ? cconj(raw[8 + j]) : raw[8 + j];
     }
     // D_c / D_r on the orbit slots m_{2i} = m0 + 512 i, m_{2i+1} = 512 (i+1) - m0
     cx<R> cd[2][8];
@@ -221,21 +248,18 @@ __device__ __forceinline__ void f1_orbit(cx<R>* w, const R* kt, const S* x, int 
             constexpr int h1 = side ^ (SW ? par(2 * P + 1) : 0);
             cx<R> lo, hi;
             bfly<sg, R>(l2[P][0], l2[P][1], k2, lo, hi);
-            w[h0 * HS + 272 * (2 * P) + pm] = lo;  // depth-3 row 2P, slot m0
-            w[h1 * HS + 272 * (2 * P + 1) + pm] = hi;
+            stc(w + h0 * HS + 272 * (2 * P) + pm, lo);  // depth-3 row 2P, slot m0
+            stc(w + h1 * HS + 272 * (2 * P + 1) + pm, hi);
         });
     });
 }
 
 // multiples of 256: blocks of 4, 2, 1 points and the chain to dct[16] / dst[16]
-template <int V, typename S, typename R>
-__device__ __forceinline__ void f1_chain(cx<R>* ch, const R* kt, const S* x, bool conj_in) {
+template <int V, typename R>
+__device__ __forceinline__ void f1_chain(cx<R>* w, const R* kt, const cx<R> (&raw)[16], bool conj_in) {
     cx<R> xs[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        xs[k] = storage<S>::ld(x + 256 * k);
-        if (conj_in) xs[k] = cconj(xs[k]);
-    }
+    for (int k = 0; k < 16; ++k) xs[k] = conj_in ? cconj(raw[k]) : raw[k];
     cx<R> c[8], d[8];
     c[0] = xs[0];
     d[0] = zero<R>();
@@ -262,7 +286,7 @@ __device__ __forceinline__ void f1_chain(cx<R>* ch, const R* kt, const S* x, boo
         for (int k = 1; k < 4; ++k) E8[8 - k] = E9[k] - b8[k];
         E8[8] = E9[0] - b8[0];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) ch[k] = E8[k];
+        for (int k = 0; k < 9; ++k) stc(w + chslot(k), E8[k]);
     }
     {
         // DST side: dst[4] = d(1024), dst[8] and dst[16] by D_n^F
@@ -273,23 +297,18 @@ __device__ __forceinline__ void f1_chain(cx<R>* ch, const R* kt, const S* x, boo
         const cx<R> E9[4] = {zero<R>(), b9[0] + E10, b9[1], b9[0] - E10};
 #pragma unroll
         for (int k = 1; k < 4; ++k) {
-            ch[8 + k] = b8[k - 1] + E9[k];
-            ch[16 - k] = b8[k - 1] - E9[k];
+            stc(w + chslot(8 + k), b8[k - 1] + E9[k]);
+            stc(w + chslot(16 - k), b8[k - 1] - E9[k]);
         }
-        ch[12] = b8[3];
+        stc(w + chslot(12), b8[3]);
     }
 }
 
 // ---------------------------------------------------------------------- F2
 template <int V, int H, typename R>
-__device__ __forceinline__ void f2_compute(cx<R>* w, const R* kt, const cx<R> (&v)[16], int P, int m0) {
+__device__ __forceinline__ void f2_compute(cx<R>* w, const R* kf, const cx<R> (&v)[16], int P, int m0) {
     constexpr bool SW = variant_traits<V>::switches;
-    int mr[16];  // slots of the orbit, increasing
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        mr[2 * i] = m0 + 32 * i;
-        mr[2 * i + 1] = 32 * (i + 1) - m0;
-    }
+    const R* kw = kf + (m0 - 1);
     cx<R> cur[16][16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) cur[0][r] = v[r];
@@ -303,7 +322,7 @@ __device__ __forceinline__ void f2_compute(cx<R>* w, const R* kt, const cx<R> (&
             constexpr int sg = H ^ (SW ? par(q) : 0);
 #pragma unroll
             for (int r = 0; r < K / 2; ++r)
-                bfly<sg, R>(cur[q][r], cur[q][K - 1 - r], kt[mr[r] << (3 + t)], nxt[2 * q][r], nxt[2 * q + 1][r]);
+                bfly<sg, R>(cur[q][r], cur[q][K - 1 - r], kw[kf2_off(t) + 15 * r], nxt[2 * q][r], nxt[2 * q + 1][r]);
         });
 #pragma unroll
         for (int q = 0; q < 2 * rows; ++q)
@@ -313,7 +332,7 @@ __device__ __forceinline__ void f2_compute(cx<R>* w, const R* kt, const cx<R> (&
     sfor<0, 16>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr int hq = H ^ (SW ? par(q) : 0);
-        w[hq * HS + 272 * P + 17 * q + m0] = cur[q][0];  // depth-7 row 16 P + q, slot m0
+        stc(w + hq * HS + 272 * P + 17 * q + m0, cur[q][0]);  // depth-7 row 16 P + q, slot m0
     });
 }
 
@@ -323,10 +342,10 @@ __device__ __forceinline__ void p3_row(cx<R>* w, const R* kt, int r7) {
     cx<R>* row = w + H * HS + 17 * r7;
     cx<R> s[15], o[15];
 #pragma unroll
-    for (int e = 0; e < 15; ++e) s[e] = row[e + 1];
+    for (int e = 0; e < 15; ++e) s[e] = ldc(row + e + 1);
     row16<V, H, R>(s, o, kt);
 #pragma unroll
-    for (int e = 0; e < 15; ++e) row[e + 1] = o[e];
+    for (int e = 0; e < 15; ++e) stc(row + e + 1, o[e]);
 }
 
 template <int V, typename S>
@@ -338,8 +357,8 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
     constexpr bool SW = variant_traits<V>::switches;
     extern __shared__ __align__(16) unsigned char smem[];
     R* kt = reinterpret_cast<R*>(smem);
-    cx<R>* w = reinterpret_cast<cx<R>*>(smem + Q4 * sizeof(R));
-    cx<R>* ch = w + WLEN;
+    R* kf = kt + Q4;
+    cx<R>* w = reinterpret_cast<cx<R>*>(smem + (Q4 + KF2_ALLOC) * sizeof(R));
     const bool conj_in = flags & 1, conj_out = flags & 2, onthefly = flags & 4;
     const int tid = threadIdx.x;
     const long long sig = blockIdx.x;
@@ -349,44 +368,64 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
     const int h = tid >> 7;  // half (= arithmetic context) of the pass's rows
     const int u = tid & 127;
 
+    // the signal's loads are issued first; the constant tables fill meanwhile
+    cx<R> raw[16];
+    f1_load<S, R>(x, tid, raw);
+
     // constants: p = 1..N/4-1 of the variant's family; p = N/8 is the base case
-    for (int p = tid; p < Q4; p += THREADS4) {
-        R v;
-        if (p == Q4 / 2) v = cos_pi_4<R>();
-        else if (!onthefly) v = ktab[(long)p << kshift];
-        else {
-            const double a = (double)p * 2.0 / (double)N4;
-            constexpr int fam = const_family(V);
-            const double d = fam == 1 ? 1.0 / (2.0 * cospi(a)) : 1.0 / (2.0 * sinpi(a));
-            v = p == 0 ? R(0) : R(d);
-        }
-        kt[p] = v;
+    auto kval = [&](int p) -> R {
+        if (p == Q4 / 2) return cos_pi_4<R>();
+        if (!onthefly) return ktab[(long)p << kshift];
+        const double a = (double)p * 2.0 / (double)N4;
+        constexpr int fam = const_family(V);
+        const double d = fam == 1 ? 1.0 / (2.0 * cospi(a)) : 1.0 / (2.0 * sinpi(a));
+        return p == 0 ? R(0) : R(d);
+    };
+    for (int p = tid; p < Q4; p += THREADS4) kt[p] = kval(p);
+    if (tid < KF2) {
+        const int t = tid < 120 ? 0 : tid < 180 ? 1 : tid < 210 ? 2 : 3;
+        const int e = tid - kf2_off(t);
+        const int r = e / 15, m0 = e - 15 * r + 1;
+        const int mr = (r & 1) ? 16 * (r + 1) - m0 : m0 + 16 * r;  // orbit slot r of m0
+        kf[tid] = kval(mr << (3 + t));
     }
     __syncthreads();
 
     // ------------------------------------------------------------------ F1
-    if (tid > 0) f1_orbit<V, S, R>(w, kt, x, tid, conj_in);
-    else f1_chain<V, S, R>(ch, kt, x, conj_in);
+    if (tid > 0) f1_orbit<V, R>(w, kt, raw, tid, conj_in);
+    else f1_chain<V, R>(w, kt, raw, conj_in);
     __syncthreads();
 
     // ------------------------------------------------------------------ F2
     {
-        const bool act = u < 120;
-        const int P = u / 15;
-        const int m0 = u - 15 * P + 1;
+        // 16-lane groups: lanes 0..14 of group P run the orbits m0 = 1..15 of
+        // depth-3 row P; lane 15 finishes the row's slots 16 e (blocks 4..7)
+        const int P = u >> 4;
+        const int wl = u & 15;
+        const bool orb = wl < 15;
+        const int m0 = wl + 1;
         cx<R> v[16];
-        if (act) {
-            const int rb = h * HS + 272 * P;
+        const int rb = h * HS + 272 * P;
+        if (orb) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                v[2 * i] = w[rb + m0 + 34 * i];                // slot m0 + 32 i
-                v[2 * i + 1] = w[rb + 34 * (i + 1) - m0 - 1];  // slot 32 (i+1) - m0
+                v[2 * i] = ldc(w + rb + m0 + 34 * i);                // slot m0 + 32 i
+                v[2 * i + 1] = ldc(w + rb + 34 * (i + 1) - m0 - 1);  // slot 32 (i+1) - m0
             }
+        } else {
+#pragma unroll
+            for (int e = 1; e < 16; ++e) v[e - 1] = ldc(w + rb + 17 * e);  // slot 16 e
         }
         __syncthreads();
-        if (act) {
-            if (h == 0) f2_compute<V, 0, R>(w, kt, v, P, m0);
-            else f2_compute<V, 1, R>(w, kt, v, P, m0);
+        if (orb) {
+            if (h == 0) f2_compute<V, 0, R>(w, kf, v, P, m0);
+            else f2_compute<V, 1, R>(w, kf, v, P, m0);
+        } else {
+            cx<R> o[15];
+            if (h == 0) row16<V, 0, R>(v, o, kt);
+            else row16<V, 1, R>(v, o, kt);
+#pragma unroll
+            for (int i = 0; i < 15; ++i) stc(w + pslot(h, 16 * P + i), o[i]);
         }
     }
     __syncthreads();
@@ -398,9 +437,10 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
 
     // ------------------------------------------------------------------ B2
     {
-        const bool blk = u < 120;
-        const int P = blk ? u / 15 : u - 120;
-        const int w15 = u - 15 * P;
+        // 16-lane groups: lane w15 < 15 of group P handles block a, child index j
+        const int P = u >> 4;
+        const int w15 = u & 15;
+        const bool blk = w15 < 15;
         const int a = w15 < 8 ? 0 : w15 < 12 ? 1 : w15 < 14 ? 2 : 3;
         const int j = w15 - (16 - (16 >> a));
         const int sp = 8 >> a;  // sub-block size of block a at depth 7
@@ -410,15 +450,11 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
             for (int q = 0; q < 16; ++q) {
                 const int hq = h ^ (SW ? par(q) : 0);
                 const int at = hq * HS + 272 * P + 17 * q + 1 + w15;
-                const cx<R> lm = w[at - 1], lp = w[at + 1];
+                const cx<R> lm = ldc(w + at - 1), lp = ldc(w + at + 1);
                 ext[q][0] = j >= 1 ? lm : zero<R>();
-                ext[q][1] = w[at];
+                ext[q][1] = ldc(w + at);
                 ext[q][2] = j + 1 < sp ? lp : zero<R>();
             }
-        } else {
-            // blocks 4..7 of depth-3 row P: its slots 16 e, e = 1..15
-#pragma unroll
-            for (int e = 1; e < 16; ++e) ext[e][1] = w[h * HS + 272 * P + 17 * e];
         }
         __syncthreads();
         if (blk) {
@@ -427,16 +463,7 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
             else bwd_run<V, 1, 4, R>(ext, o);
             cx<R>* dst = w + h * HS + 272 * P + 17 * (w15 + 1);  // block a at 16 + 16 w15 of the row
 #pragma unroll
-            for (int e = 0; e < 16; ++e) dst[e] = o[e];
-        } else {
-            cx<R> s[15], o[15];
-#pragma unroll
-            for (int e = 0; e < 15; ++e) s[e] = ext[e + 1][1];
-            if (h == 0) row16<V, 0, R>(s, o, kt);
-            else row16<V, 1, R>(s, o, kt);
-            cx<R>* dst = w + h * HS + 272 * P + 1;
-#pragma unroll
-            for (int e = 0; e < 15; ++e) dst[e] = o[e];
+            for (int e = 0; e < 16; ++e) stc(dst + e, o[e]);
         }
     }
     __syncthreads();
@@ -457,16 +484,19 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
         const bool act = p > 0;
         cx<R> ext[2][8][3];
         if (act) {
-            const int om = pad(p - 1), o0 = pad(p), op = pad(p + 1);
+            // blocks 4..7 (p < 16) sit in pad slots 16 q + p - 1 (stride 17)
+            const int o0 = p < 16 ? 17 * (p - 1) + 16 : pad(p);
+            const int om = p < 16 ? (p > 1 ? o0 - 17 : o0) : pad(p - 1);
+            const int op = p < 16 ? o0 + 17 : pad(p + 1);
 #pragma unroll
             for (int side = 0; side < 2; ++side)
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int hq = side ^ (SW ? par(q) : 0);
                     const cx<R>* row = w + hq * HS + 272 * q;
-                    const cx<R> lm = row[om], lp = row[op];
+                    const cx<R> lm = ldc(row + om), lp = ldc(row + op);
                     ext[side][q][0] = j >= 1 ? lm : zero<R>();
-                    ext[side][q][1] = row[o0];
+                    ext[side][q][1] = ldc(row + o0);
                     ext[side][q][2] = j + 1 < sp ? lp : zero<R>();
                 }
         }
@@ -476,10 +506,10 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
             cx<R> o[8];
             bwd_run<V, 0, 3, R>(ext[0], o);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) w[ob + e] = o[e];
+            for (int e = 0; e < 8; ++e) stc(w + ob + e, o[e]);
             bwd_run<V, 1, 3, R>(ext[1], o);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) w[HS + ob + e] = o[e];
+            for (int e = 0; e < 8; ++e) stc(w + HS + ob + e, o[e]);
         }
     }
     __syncthreads();
@@ -529,16 +559,16 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
                 }
                 e8 = done ? 0 : kk;  // D_8(kk), kk in 1..7, unless the path ended at a q_a
                 const R wd = done ? R(0) : sgn;
-                cx<R> accs = ch[8 + e8] * wd;
+                cx<R> accs = ldc(w + chslot(8 + e8)) * wd;
 #pragma unroll
                 for (int t = 0; t < 5; ++t) {
-                    const cx<R> o = w[HS + bo(3 + t) + pad(is[t] - 1)];
+                    const cx<R> o = ldc(w + HS + bo(3 + t) + pad(is[t] - 1));
                     accs = cx<R>{accs.re + ws[t] * o.re, accs.im + ws[t] * o.im};
                 }
-                cx<R> accc = ch[ic[4]];
+                cx<R> accc = ldc(w + chslot(ic[4]));
 #pragma unroll
                 for (int t = 0; t < 5; ++t) {
-                    const cx<R> o = w[bo(3 + t) + pad(ic[t])];
+                    const cx<R> o = ldc(w + bo(3 + t) + pad(ic[t]));
                     accc = cx<R>{accc.re + wc[t] * o.re, accc.im + wc[t] * o.im};
                 }
                 // levels 2, 1, 0 on the orbit {k0, 512-k0, 512+k0, 1024-k0, ...}
@@ -546,26 +576,26 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
                 const int pA = pad(kA), pB = pad(kB), pC = pA + 544, pD = pB + 544;
                 const int qA = pad(kA - 1), qB = pad(kB - 1), qC = qA + 544, qD = qB + 544;
                 const cx<R> Ec3 = accc, Es3 = accs;
-                const cx<R> oc2 = w[bo(2) + pA];
+                const cx<R> oc2 = ldc(w + bo(2) + pA);
                 const cx<R> c2a = Ec3 + oc2, c2b = Ec3 - oc2;  // E_2(k0), E_2(512-k0)
-                const cx<R> o1a = w[bo(1) + pA], o1b = w[bo(1) + pB];
+                const cx<R> o1a = ldc(w + bo(1) + pA), o1b = ldc(w + bo(1) + pB);
                 const cx<R> c1[4] = {c2a + o1a, c2b + o1b, c2b - o1b, c2a - o1a};
                 const int pk[4] = {pA, pB, pC, pD}, qk[4] = {qA, qB, qC, qD};
                 cx<R> C[8];  // E_0 at kA, kB, kC, kD, 2048-kD, 2048-kC, 2048-kB, 2048-kA
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const cx<R> o0 = w[pk[i]];
+                    const cx<R> o0 = ldc(w + pk[i]);
                     C[i] = c1[i] + o0;
                     C[7 - i] = c1[i] - o0;
                 }
-                const cx<R> os2 = w[HS + bo(2) + qA];
+                const cx<R> os2 = ldc(w + HS + bo(2) + qA);
                 const cx<R> s2a = os2 + Es3, s2b = os2 - Es3;
-                const cx<R> p1a = w[HS + bo(1) + qA], p1b = w[HS + bo(1) + qB];
+                const cx<R> p1a = ldc(w + HS + bo(1) + qA), p1b = ldc(w + HS + bo(1) + qB);
                 const cx<R> s1[4] = {p1a + s2a, p1b + s2b, p1b - s2b, p1a - s2a};
                 cx<R> Dd[8];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const cx<R> o0 = w[HS + qk[i]];
+                    const cx<R> o0 = ldc(w + HS + qk[i]);
                     Dd[i] = o0 + s1[i];
                     Dd[7 - i] = o0 - s1[i];
                 }
@@ -578,12 +608,13 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
                 }
             }
         } else {
-            auto Oc = [&](int a, int k) { return w[pad(2048 - (2048 >> a) + k)]; };
-            auto Os = [&](int a, int k) { return w[HS + pad(2048 - (2048 >> a) + k - 1)]; };
+            auto Oc = [&](int a, int k) { return ldc(w + pad(2048 - (2048 >> a) + k)); };
+            auto Os = [&](int a, int k) { return ldc(w + HS + pad(2048 - (2048 >> a) + k - 1)); };
             // harmonics 0, 256, ..., 2048
-            const cx<R> E3_0 = ch[0] + Oc(3, 0) + Oc(4, 0) + Oc(5, 0) + Oc(6, 0) + Oc(7, 0);
+            const cx<R> e8_0 = ldc(w + chslot(0));
+            const cx<R> E3_0 = e8_0 + Oc(3, 0) + Oc(4, 0) + Oc(5, 0) + Oc(6, 0) + Oc(7, 0);
             // E_3(256), the top harmonic of periodization 512: E_4(0) - O_3(0)
-            const cx<R> E3_256 = ch[0] - Oc(3, 0) + Oc(4, 0) + Oc(5, 0) + Oc(6, 0) + Oc(7, 0);
+            const cx<R> E3_256 = e8_0 - Oc(3, 0) + Oc(4, 0) + Oc(5, 0) + Oc(6, 0) + Oc(7, 0);
             const cx<R> o2 = Oc(2, 0);
             const cx<R> E2_0 = E3_0 + o2, E2_512 = E3_0 - o2, E2_256 = E3_256;
             const cx<R> o1_0 = Oc(1, 0), o1_256 = Oc(1, 256);
@@ -626,7 +657,7 @@ __global__ __launch_bounds__(THREADS4) void amqft_a4096_kernel(const S* __restri
 
 template <typename R>
 constexpr size_t a4096_lds() {
-    return Q4 * sizeof(R) + (WLEN + CHLEN) * sizeof(cx<R>);
+    return (Q4 + KF2_ALLOC) * sizeof(R) + WLEN * sizeof(cx<R>);
 }
 
 template <int V, typename S>
