@@ -180,6 +180,231 @@ def cpu_baseline(x_np, n: int, variant: int, target_s: float = 12.0):
                       % (sample, n, variant, el)}
 
 
+
+def _rel(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    nb = np.linalg.norm(b.ravel())
+    return float(np.linalg.norm((a - b).ravel()) / nb) if nb > 0 else float(np.linalg.norm(a.ravel()))
+
+
+def _event_time(fn, reps: int, stream, between=None):
+    """Per-rep HIP-event times of fn on the stream; `between` runs outside the
+    timed events before every rep (e.g. a cache scrub)."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        if between is not None:
+            between()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return {"avg_ms": sum(ts) / len(ts), "median_ms": ts[len(ts) // 2], "min_ms": ts[0]}
+
+
+def bench_fp64_small(args, stream):
+    """64 x N=256 complex128, U[-1,1), seed 0, variant 4: latency-bound."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1404_1810_amd import _lib, api, inputs
+    x_np = inputs.cfg_fp64_n256()
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.empty_like(x)
+    plan = api.get_plan(256, 64, 4, _lib.C128)
+    r = time_launches(lambda: plan.exec(x, out=y), max(args.steps, 50), args.warmup, stream)
+    plan.exec(x, out=y)
+    torch.cuda.synchronize()
+    err = _rel(y.cpu().numpy(), oracle.cdft(x_np, 4))
+    fl = flops_5nlogn(256, 64)
+    return {"workload": "batch 64 x N=256 complex128, re/im U[-1,1) seed 0, forward, variant 4",
+            "kernel": plan.describe(), "avg_ms": round(r["avg_ms"], 5), "median_ms": round(r["median_ms"], 5),
+            "min_ms": round(r["min_ms"], 5), "gflops": round(fl / r["avg_ms"] / 1e6, 2),
+            "rel_l2_vs_oracle": err, "bound": "latency (0.5 MB moved)"}
+
+
+def bench_uneven(args, stream):
+    """20000 FP32 signals of lengths 2^4..2^16 (seed 2), entries N(0,1) (seed 3),
+    variant 4: one fused plan (persistent kernel + long-length classes,
+    autotuned, graph-replayed) against gather -> one batched plan per length ->
+    scatter (B2) and against one launch per signal (B1)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1404_1810_amd import _lib, api, inputs
+    t0 = time.time()
+    lengths, offsets = inputs.uneven_lengths()
+    buf = inputs.uneven_entries(lengths, offsets)
+    total = int(offsets[-1])
+    log("uneven: %d signals, %d points, generated in %.1f s" % (len(lengths), total, time.time() - t0))
+    x = torch.from_numpy(buf).cuda()
+    y = torch.empty_like(x)
+    mp = api.ManyPlan(lengths, offsets, 4, _lib.C64)
+    mp.exec(x, out=y)  # first out-of-place execution autotunes
+    torch.cuda.synchronize()
+    fused_eager = time_launches(lambda: mp.exec(x, out=y), args.steps, args.warmup, stream)
+    fused_graph = time_launches(lambda: mp.exec(x, out=y, graph=True), args.steps, args.warmup, stream)
+    # B2: gather by length, batched plan per length, scatter back
+    classes = []
+    off_t = torch.from_numpy(offsets[:-1])
+    for k in np.unique(lengths):
+        sel = np.nonzero(lengths == k)[0]
+        starts = off_t[torch.from_numpy(sel)]
+        idx = (starts[:, None] + torch.arange(int(k))[None, :]).reshape(-1).cuda()
+        rows = torch.empty((len(sel), int(k)), dtype=torch.complex64, device="cuda")
+        outs = torch.empty_like(rows)
+        classes.append((idx, rows, outs, api.get_plan(int(k), len(sel), 4, _lib.C64)))
+    y2 = torch.empty_like(x)
+
+    def plain():
+        for idx, rows, outs, pl in classes:
+            torch.index_select(x, 0, idx, out=rows.view(-1))
+            pl.exec(rows, out=outs)
+            y2.index_copy_(0, idx, outs.view(-1))
+    plain_r = time_launches(plain, max(3, args.steps // 4), 1, stream)
+    # B1: one launch per signal (plans cached per length, batch 1)
+    singles = [api.get_plan(int(n), 1, 4, _lib.C64) for n in lengths]
+    y3 = torch.empty_like(x)
+
+    def per_signal():
+        for i, pl in enumerate(singles):
+            o, n = int(offsets[i]), int(lengths[i])
+            pl.exec(x[o:o + n], out=y3[o:o + n])
+    b1 = time_launches(per_signal, 2, 1, stream)
+    torch.cuda.synchronize()
+    yf = y.cpu().numpy()
+    # accuracy: fused vs plain (same relations, different kernels) and vs the
+    # FP64 oracle on one signal of every length
+    err_plain = _rel(yf, y2.cpu().numpy())
+    worst = 0.0
+    for k in np.unique(lengths):
+        i = int(np.nonzero(lengths == k)[0][0])
+        o, n = int(offsets[i]), int(lengths[i])
+        ref = oracle.cdft(buf[o:o + n].astype(np.complex128)[None, :], 4)[0]
+        worst = max(worst, _rel(yf[o:o + n], ref))
+    algo = total * 16.0
+    return {"workload": "20000 complex64 signals, N=2^k, k uniform on {4..16} (seed 2), entries N(0,1) (seed 3), "
+                        "packed, int64 offsets, variant 4",
+            "points": total, "plan": mp.describe(),
+            "fused_graph_ms": round(fused_graph["avg_ms"], 4), "fused_eager_ms": round(fused_eager["avg_ms"], 4),
+            "plain_gather_batched_scatter_ms": round(plain_r["avg_ms"], 4),
+            "per_signal_launches_ms": round(b1["avg_ms"], 3),
+            "speedup_vs_plain": round(plain_r["avg_ms"] / fused_graph["avg_ms"], 3),
+            "speedup_vs_per_signal": round(b1["avg_ms"] / fused_graph["avg_ms"], 2),
+            "fused_hbm_gbs": round(algo / fused_graph["avg_ms"] / 1e6, 1),
+            "fused_frac_of_peak": round(algo / fused_graph["avg_ms"] / 1e6 / HBM_PEAK_GBS, 4),
+            "rel_l2_fused_vs_plain": err_plain, "max_rel_l2_vs_oracle_one_per_length": worst}
+
+
+def bench_grad(args, stream):
+    """Fused loss/gradient: batch 4096 x N=1024 complex64 (x seed 0, W seed 1),
+    loss = sum |W * F x|^2, grad = 2 F^H(|W|^2 F x); cold cache (a 512 MB
+    scrub between reps, outside the events); also the autograd path and a
+    65536-signal batch."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1404_1810_amd import _lib, api, inputs
+    xn, wn = inputs.cfg_grad()
+    x = torch.from_numpy(xn).cuda()
+    w = torch.from_numpy(wn).cuda()
+    plan = api.get_plan(1024, 4096, 4, _lib.C64)
+    scrub = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+
+    def do_scrub():
+        scrub.fill_(1)
+    for _ in range(args.warmup):
+        plan.power_loss_grad(x, w)
+    fused = _event_time(lambda: plan.power_loss_grad(x, w), args.steps, stream, do_scrub)
+
+    def autograd_step():
+        xr = x.detach().requires_grad_(True)
+        yv = api.amqft(xr, 4)
+        loss = (torch.abs(w * yv) ** 2).sum()
+        loss.backward()
+        return xr.grad
+    for _ in range(args.warmup):
+        autograd_step()
+    auto = _event_time(autograd_step, max(3, args.steps // 2), stream, do_scrub)
+    loss, g = plan.power_loss_grad(x, w)
+    torch.cuda.synchronize()
+    # accuracy on 4 signals against the oracle's closed form
+    Xo = oracle.cdft(xn[:4].astype(np.complex128), 4)
+    go = 2.0 * oracle.cdft_adjoint(np.abs(wn[:4].astype(np.complex128)) ** 2 * Xo, 4)
+    lo = (np.abs(wn[:4].astype(np.complex128) * Xo) ** 2).sum(axis=1)
+    err_g = _rel(g[:4].cpu().numpy(), go)
+    err_l = _rel(loss[:4].cpu().numpy(), lo)
+    algo = 4096 * 1024 * 24.0
+    out = {"workload": "batch 4096 x N=1024 complex64, x ~ N(0,1) seed 0, W ~ N(0,1) seed 1, "
+                       "loss = sum |W F x|^2 and its gradient, variant 4, cold cache",
+           "fused_ms": round(fused["avg_ms"], 5), "fused_hbm_gbs": round(algo / fused["avg_ms"] / 1e6, 1),
+           "autograd_fwd_bwd_ms": round(auto["avg_ms"], 4),
+           "rel_l2_grad_vs_oracle": err_g, "rel_l2_loss_vs_oracle": err_l}
+    del x, w
+    # large batch for the bandwidth figure (inputs beyond the last-level cache)
+    B = 65536
+    xl = torch.empty((B, 1024), dtype=torch.complex64, device="cuda")
+    wl = torch.empty_like(xl)
+    for s0, rows in inputs.chunks("normal", inputs.SEEDS["grad_x"], B, 1024, chunk=4096):
+        xl[s0:s0 + len(rows)].copy_(torch.from_numpy(rows.astype(np.complex64)))
+    for s0, rows in inputs.chunks("normal", inputs.SEEDS["grad_w"], B, 1024, chunk=4096):
+        wl[s0:s0 + len(rows)].copy_(torch.from_numpy(rows.astype(np.complex64)))
+    pl = api.get_plan(1024, B, 4, _lib.C64)
+    big = time_launches(lambda: pl.power_loss_grad(xl, wl), args.steps, args.warmup, stream)
+    algo_l = B * 1024 * 24.0
+    out.update({"large_batch": B, "large_fused_ms": round(big["avg_ms"], 4),
+                "large_hbm_gbs": round(algo_l / big["avg_ms"] / 1e6, 1),
+                "large_frac_of_peak": round(algo_l / big["avg_ms"] / 1e6 / HBM_PEAK_GBS, 4),
+                "kernel": pl.describe()})
+    return out
+
+
+def bench_precision(args, stream):
+    """1024 x N=2^20, FP16 (and BF16) storage of U[-1,1) entries (seed 0), FP32
+    arithmetic, on-the-fly constants, all 8 variants: time and GB/s per variant,
+    relative L2 error against the FP64 oracle on the same stored input for a
+    few sampled signals."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1404_1810_amd import _lib, api, inputs
+    n = 1 << 20
+    B = args.batch if args.batch != 16384 else 1024
+    xh = torch.empty((B, n, 2), dtype=torch.float16, device="cuda")
+    for s0 in range(0, B, 8):
+        m = min(8, B - s0)
+        xh[s0:s0 + m].copy_(torch.from_numpy(inputs.cfg_fp16_rows(m, n, start=s0)))
+    yh = torch.empty_like(xh)
+    sample = [0, B // 2, B - 1][: min(3, B)]
+    xs = xh[sample].float().cpu().numpy()
+    xs = xs[..., 0].astype(np.float64) + 1j * xs[..., 1].astype(np.float64)
+    ref = oracle.cdft(xs, 2)  # FP64 truth on the stored (quantised) input
+    res = {}
+    for v in range(1, 9):
+        plan = api.Plan(n, B, v, _lib.C32H, _lib.FLAG_ONTHEFLY_CONSTANTS)
+        r = time_launches(lambda: plan.exec(xh, out=yh), max(3, args.steps // 4), 1, stream)
+        got = yh[sample].float().cpu().numpy()
+        got = got[..., 0].astype(np.float64) + 1j * got[..., 1].astype(np.float64)
+        nonfinite = int((~np.isfinite(got)).sum())
+        res[str(v)] = {"avg_ms": round(r["avg_ms"], 3),
+                       "hbm_gbs": round(B * n * 8.0 / r["avg_ms"] / 1e6, 1),
+                       "rel_l2_vs_fp64_oracle": _rel(got, ref) if nonfinite == 0 else None,
+                       "nonfinite_outputs": nonfinite}
+        log("precision variant %d: %.3f ms, rel L2 %s" % (v, r["avg_ms"], res[str(v)]["rel_l2_vs_fp64_oracle"]))
+        plan.close()
+    return {"workload": "batch %d x N=2^20, fp16 storage, re/im U[-1,1) seed 0, fp32 arithmetic, "
+                        "on-the-fly constants" % B, "sampled_signals": sample, "variants": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +421,10 @@ def main():
     ap.add_argument("--ingest-pmc", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the traffic record from rocprofv3 counter files (no GPU work)")
     ap.add_argument("--kernel-desc", default="", help="kernel description for --ingest-pmc")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the FP64, uneven-batch and fused-gradient workloads")
+    ap.add_argument("--workload", default="headline", choices=["headline", "precision"],
+                    help="precision: the 2^20-point FP16 accuracy/throughput study instead")
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(args, *args.ingest_pmc)
@@ -210,11 +439,20 @@ def main():
 
     from paper_1404_1810_amd import api, inputs
 
+    if args.workload == "precision":
+        stream = torch.cuda.current_stream()
+        res = bench_precision(args, stream)
+        print(json.dumps({"metric": "fp16-storage AM-QFT: GB/s and relative L2 error per variant, N=2^20",
+                          "n_gpus": 1, "data": "synthetic", "dtype": "f16 storage, f32 arithmetic",
+                          "config": {"workload": res["workload"]}, "variants": res["variants"],
+                          "sampled_signals": res["sampled_signals"]}), flush=True)
+        return
+
     n, batch = args.n, args.batch
     log("generating %d x %d complex64 (seed %d)" % (batch, n, inputs.SEEDS["fp32_n4096"]))
     t0 = time.time()
     x = torch.empty((batch, n), dtype=torch.complex64, device="cuda")
-    head_rows = min(batch, 4096)
+    head_rows = min(batch, 8192)
     x_np = np.empty((head_rows, n), dtype=np.complex64)  # rows kept for the CPU checks
     for s0, rows in inputs.chunks("normal", inputs.SEEDS["fp32_n4096"], batch, n):
         r32 = rows.astype(np.complex64)
@@ -285,6 +523,19 @@ def main():
                               "gflops": round(fl / r["avg_ms"] / 1e6, 1),
                               "hbm_gbs": round(algo_bytes / r["avg_ms"] / 1e6, 1)} for v, r in results.items()},
     }
+    if not args.no_extra:
+        del x, y
+        torch.cuda.empty_cache()
+        extra = {}
+        log("FP64 latency workload")
+        extra["fp64_n256"] = bench_fp64_small(args, stream)
+        log("uneven-length workload")
+        extra["uneven"] = bench_uneven(args, stream)
+        torch.cuda.empty_cache()
+        log("fused loss/gradient workload")
+        extra["grad"] = bench_grad(args, stream)
+        torch.cuda.empty_cache()
+        line["workloads"] = extra
     tr = load_traffic(family, args.variant, n, batch)
     if tr is not None:
         line["roofline"]["traffic"] = round(tr["traffic_bytes_per_launch"])
