@@ -122,14 +122,13 @@ def ingest_pmc(args, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
     the transform run and of the --copy-calibration run) into the traffic
     record bench.py reports.  Counters are KiB per dispatch; each is scaled by
     the factor that maps the copy kernel's reading to its known byte count."""
-    from paper_1404_1810_amd import api  # noqa: F401  (plan description needs the library)
     n, batch = args.n, args.batch
     desc = args.kernel_desc
     family = kernel_family(desc)
     fk, nd = _pmc_per_dispatch(fetch_csv, "FETCH_SIZE", family)
     wk, _ = _pmc_per_dispatch(write_csv, "WRITE_SIZE", family)
-    fc, _ = _pmc_per_dispatch(copy_fetch_csv, "FETCH_SIZE", "elementwise")
-    wc, _ = _pmc_per_dispatch(copy_write_csv, "WRITE_SIZE", "elementwise")
+    fc, _ = _pmc_per_dispatch(copy_fetch_csv, "FETCH_SIZE", "neg_kernel")
+    wc, _ = _pmc_per_dispatch(copy_write_csv, "WRITE_SIZE", "neg_kernel")
     copy_bytes = batch * n * 8.0
     f_read = copy_bytes / (fc * 1024.0)
     f_write = copy_bytes / (wc * 1024.0)
