@@ -474,11 +474,13 @@ amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_
     // group the signals by length
     std::vector<std::vector<int64_t>> by(AMQFT_MAX_LOG2N + 1);
     for (int64_t i = 0; i < count; ++i) by[log2_exact(lengths_host[i])].push_back(offsets_host[i]);
-    // persistent work list: lengths up to kPersistentMaxLog2, items of up to
-    // 256/T signals of one length, longest length first
+    // persistent work list: the lengths without a compile-time kernel (up to
+    // kPersistentMaxLog2, or below 2^8 where one exists), items of up to 256/T
+    // signals of one length, longest length first
+    const int pmax = kA_supported(p->variant, 8, p->dtype) ? 7 : kPersistentMaxLog2;
     std::vector<int> items;  // 4 ints per item
     std::vector<long long> poffs;
-    for (int l = kPersistentMaxLog2; l >= 0; --l) {
+    for (int l = pmax; l >= 0; --l) {
         const std::vector<int64_t>& v = by[l];
         if (v.empty()) continue;
         length_class c;
@@ -512,7 +514,7 @@ amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_
         p->grid = std::max(1, std::min(4 * cus, p->nitems));
     }
     // longer lengths: one single-length plan per class over the packed buffer
-    for (int l = kPersistentMaxLog2 + 1; l <= AMQFT_MAX_LOG2N; ++l) {
+    for (int l = pmax + 1; l <= AMQFT_MAX_LOG2N; ++l) {
         const std::vector<int64_t>& v = by[l];
         if (v.empty()) continue;
         length_class c;

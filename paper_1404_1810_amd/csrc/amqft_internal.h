@@ -60,6 +60,7 @@ struct loss_launch {
 
 // Fused loss/gradient kernel (forward, |w|^2 weighting, adjoint).
 hipError_t launch_loss(const loss_launch& a, hipStream_t stream);
+hipError_t launch_kA_loss(const loss_launch& a, hipStream_t stream);
 
 // Fast kernels with compile-time geometry (N = 64 .. 4096, FP32 / FP64).
 bool fast_supported(int logn, int dtype);
@@ -67,12 +68,14 @@ hipError_t launch_fast(const lds_launch& a, hipStream_t stream);
 hipError_t prime_fast(int variant, int dtype);
 void fast_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
 
-// Skeleton-A kernel for N = 4096 (variants 4 and 8, FP32 / FP64) with its
-// dataflow fixed at compile time (amqft_k4096.hip).
-bool a4096_supported(int variant, int logn, int dtype);
-hipError_t launch_a4096(const lds_launch& a, hipStream_t stream);
-hipError_t prime_a4096(int variant, int dtype);
-void a4096_shape(int dtype, int* threads, size_t* lds_bytes);
+// Skeleton-A kernels for N = 2^8 .. 2^14 (variants 4 and 8; FP64 up to 2^13)
+// with the dataflow fixed at compile time (amqft_kA.hip).
+bool kA_supported(int variant, int logn, int dtype);
+hipError_t launch_kA(const lds_launch& a, hipStream_t stream);
+hipError_t prime_kA(int variant, int dtype);
+void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
+// fused loss / gradient on the same kernels (forward, weighting, adjoint)
+bool kA_loss_supported(int variant, int logn, int dtype);
 
 // Name and launch shape of the kernel launch_lds picks for a (for reports).
 void describe_lds(const lds_launch& a, char* buf, size_t len);

@@ -1,0 +1,1047 @@
+// Skeleton-A AM-QFT (variants 4 and 8) for N = 2^8 .. 2^14 with the whole
+// dataflow fixed at compile time: a handful of passes over LDS, each reading
+// everything it needs, waiting at a barrier and writing, every thread
+// holding 16 complex values per pass.
+//
+// View of one side (DCT or DST, H = N/2 positions): after the forward levels
+// 0..l-1 of dct_ot / dst_ot the data form 2^l rows of W_l = H / 2^l slots;
+// slot m of a row holds the element of chain block a = v2(m) (the ot
+// function of periodization N / 2^a) with odd index m / 2^a.  A forward level
+// pairs slot m with W_l - m inside a row and sends sum / difference to rows
+// 2P / 2P+1 at the same slot (D_k, Table tab:elabora_relations_B), the hi half
+// scaled by the M4 / M8 constant of index p = m * 2^l (Sec. 7.1; table entry
+// N/8 is set to cos(pi/4), the L = 8 base case).
+//
+// Passes (D = log2 N - 2):
+//   F1   load, D_c / D_r, levels 0..2 on the orbits {+-m0 + (N/8) j}; thread
+//        m0 = 0 of a signal does the blocks of 4, 2, 1 points and the chain
+//        up to dct[16] / dst[16].
+//   M_k  middle levels in one or two orbit passes of r <= 4 levels on the
+//        orbits {+-m0 + 2G j} of each row (G = W / 2^r lanes per row); lane
+//        m0 = 0 of a row finishes the slots that are multiples of G (whole
+//        sub-blocks of at most 2^(r-1) points) in registers.
+//   P3   rows of 16 slots at depth D-3: sub-blocks of 8, 4, 2, 1 points,
+//        forward and backward in registers.
+//   B_k  mirror of M_k: a thread combines one child index j of 2^r rows into
+//        2^r consecutive parent harmonics, with the +-1 neighbours M4 / M8 read.
+//   B0   mirror of F1 (levels 2..0), both sides per thread.
+//   C0   chain D_n^F: levels 3..D-3 along each output's reflection path,
+//        levels 0..2 on an orbit of 8 harmonics, D_c and the store.
+//
+// Storage per signal: two LDS halves (contexts: row (side, path) lives in
+// half side ^ parity(path) for M8, in half side for M4), positions padded by
+// one slot per 16.  The pad slots (index k at 17 k + 16) hold what the orbit
+// passes finish early: row R of pass k stores its values at the first pad
+// slot of its child rows 1 .. 2^r - 1, so no two passes collide; the first
+// pad slot of the eight depth-3 rows of each half holds the chain values.
+#include <type_traits>
+
+#include "amqft_device.h"
+#include "amqft_internal.h"
+#include "amqft_leaf.h"
+
+namespace amqft {
+
+namespace {
+
+constexpr int par(int x) { return x ? ((x & 1) ^ par(x >> 1)) : 0; }
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+__device__ __forceinline__ int pad(int p) { return p + (p >> 4); }
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ cx<R> zero() { return cx<R>{R(0), R(0)}; }
+
+template <int SG, typename R>
+__device__ __forceinline__ void bfly(cx<R> x, cx<R> y, R k, cx<R>& lo, cx<R>& hi) {
+    if constexpr (SG == 0) {
+        lo = x + y;
+        hi = (x - y) * k;
+    } else {
+        lo = x - y;
+        hi = (x + y) * k;
+    }
+}
+
+// M^F of one child index in parent context SG (hm, h0, hp = F[i-1], F[i], F[i+1])
+template <int V, int SG, typename R>
+__device__ __forceinline__ cx<R> mf(cx<R> hm, cx<R> h0, cx<R> hp) {
+    if constexpr (V == 4) return SG == 0 ? h0 + hp : hm + h0;
+    else return SG == 0 ? h0 - hm : h0 - hp;
+}
+
+// one backward level on runs extended by one halo each side (L, Hh: n + 2
+// children values; P: 2n + 2 parent values).  Halos out of reach come out as
+// zero; M4 / M8 only consume a hi child's halo on the side its lo child fills.
+template <int V, int SG, int n, typename R>
+__device__ __forceinline__ void combine(const cx<R>* L, const cx<R>* Hh, cx<R>* P) {
+#pragma unroll
+    for (int rho = -1; rho <= 2 * n; ++rho) {
+        const bool even = ((rho + 2) & 1) == 0;
+        const int i = even ? rho / 2 : (rho - 1) / 2;
+        if ((SG == 0) == even) {
+            P[rho + 1] = L[i + 1];
+        } else {
+            const cx<R> hm = i >= 0 ? Hh[i] : zero<R>();
+            const cx<R> hp = i + 1 <= n ? Hh[i + 2] : zero<R>();
+            P[rho + 1] = mf<V, SG, R>(hm, Hh[i + 1], hp);
+        }
+    }
+}
+
+template <int V, int SGB, int r, int t, typename R>
+__device__ __forceinline__ void bwd_levels(cx<R> (&cur)[1 << r][(1 << r) + 2]) {
+    if constexpr (t < r) {
+        constexpr bool SW = variant_traits<V>::switches;
+        constexpr int nrow = 1 << (r - t - 1);
+        constexpr int n = 1 << t;
+        sfor<0, nrow>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int sg = SGB ^ (SW ? par(q) : 0);
+            cx<R> tmp[2 * n + 2];
+            combine<V, sg, n, R>(cur[2 * q], cur[2 * q + 1], tmp);
+#pragma unroll
+            for (int e = 0; e < 2 * n + 2; ++e) cur[q][e] = tmp[e];
+        });
+        bwd_levels<V, SGB, r, t + 1, R>(cur);
+    }
+}
+
+// r backward levels from 2^r rows below a parent of context SGB for one child
+// index j: ext[q] = {F[j-1], F[j], F[j+1]}; out = parent values 2^r j ...
+template <int V, int SGB, int r, typename R>
+__device__ __forceinline__ void bwd_run(const cx<R> (&ext)[1 << r][3], cx<R>* out) {
+    cx<R> cur[1 << r][(1 << r) + 2];
+#pragma unroll
+    for (int q = 0; q < (1 << r); ++q) {
+        cur[q][0] = ext[q][0];
+        cur[q][1] = ext[q][1];
+        cur[q][2] = ext[q][2];
+    }
+    bwd_levels<V, SGB, r, 0, R>(cur);
+#pragma unroll
+    for (int e = 0; e < (1 << r); ++e) out[e] = cur[0][e + 1];
+}
+
+// whole sub-blocks of a row of 2^r slots in context SG: s[e-1] = slot e,
+// e = 1 .. 2^r - 1 (blocks of 2^(r-1-b) points at slots (2i+1) 2^b);
+// o = their spectra, block-contiguous, block of sz points at 2^r - 2 sz
+template <int V, int SG, int r, typename R>
+__device__ __forceinline__ void rowk(const cx<R>* s, cx<R>* o, const R* kt, int D) {
+    sfor<0, r>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        constexpr int sz = 1 << (r - 1 - b);
+        cx<R> blk[sz];
+#pragma unroll
+        for (int i = 0; i < sz; ++i) blk[i] = s[((2 * i + 1) << b) - 1];
+        leaf::ot<V, sz, SG, R>(blk, kt, D);
+#pragma unroll
+        for (int i = 0; i < sz; ++i) o[(1 << r) - 2 * sz + i] = blk[i];
+    });
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+template <int LOGN>
+struct kgeo {
+    static constexpr int N = 1 << LOGN, H = N / 2, D = LOGN - 2, Q = N / 4;
+    static constexpr int T = N / 16;                 // threads per signal (= depth-3 row width W3)
+    static constexpr int WG = T >= 256 ? T : 256;    // threads per workgroup
+    static constexpr int SPW = WG / T;               // signals per workgroup
+    static constexpr int W3 = H / 8, W3P = W3 + W3 / 16;
+    static constexpr int HS = H + H / 16;            // padded positions of one half
+    static constexpr int GUARD = 32;
+    static constexpr int SL = 2 * HS + GUARD;        // complex slots per signal
+    static constexpr int NMID = D - 6;               // levels between F1 and P3
+    static constexpr int NP = NMID > 0 ? (NMID + 3) / 4 : 0;
+    static constexpr int rk(int k) { return NMID / NP + (k < NMID % NP ? 1 : 0); }
+    static constexpr int lk(int k) { return k == 0 ? 3 : lk(k - 1) + rk(k - 1); }
+    static constexpr int Wk(int k) { return H >> lk(k); }
+    static constexpr int Gk(int k) { return Wk(k) >> rk(k); }
+    // stride-1 constant tables of the middle passes: [t][rho][m - 1]
+    static constexpr int kfsize(int k) { return (Gk(k) - 1) * ((1 << rk(k)) - 1); }
+    static constexpr int kfbase(int k) { return k == 0 ? 0 : kfbase(k - 1) + kfsize(k - 1); }
+    static constexpr int KF = NP > 0 ? kfbase(NP - 1) + kfsize(NP - 1) : 0;
+    static constexpr int KF_ALLOC = (KF + 3) & ~3;
+    static constexpr int kft(int k, int t) { return (Gk(k) - 1) * ((1 << rk(k)) - (1 << (rk(k) - t))); }
+};
+
+template <typename R, int LOGN>
+constexpr size_t kA_lds_bytes() {
+    using G = kgeo<LOGN>;
+    return (size_t)(G::Q + G::KF_ALLOC) * sizeof(R) + (size_t)G::SPW * G::SL * sizeof(cx<R>);
+}
+
+// ---------------------------------------------------------------------------
+// F1
+// ---------------------------------------------------------------------------
+template <int LOGN, typename S, typename R>
+__device__ __forceinline__ void f1_load(const S* x, int m0, bool live, cx<R> (&raw)[16]) {
+    constexpr int N8 = (1 << LOGN) / 8, N16 = (1 << LOGN) / 16;
+    if (!live) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) raw[j] = zero<R>();
+    } else if (m0 > 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            raw[j] = storage<S>::ld(x + m0 + N8 * j);
+            raw[8 + j] = storage<S>::ld(x + N8 * (j + 1) - m0);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) raw[k] = storage<S>::ld(x + N16 * k);
+    }
+}
+
+template <int V, int LOGN, typename R>
+__device__ __forceinline__ void f1_orbit(cx<R>* w, const R* kt, const cx<R> (&raw)[16], int m0, bool conj_in) {
+    using G = kgeo<LOGN>;
+    constexpr bool SW = variant_traits<V>::switches;
+    constexpr int N8 = G::N / 8, N4 = G::N / 4;
+    cx<R> xa[8], xb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        xa[j] = conj_in ? cconj(raw[j]) : raw[j];
+        xb[j] = conj_in ? cconj(raw[8 + j]) : raw[8 + j];
+    }
+    cx<R> cd[2][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        cd[0][2 * i] = xa[i] + xb[7 - i];
+        cd[1][2 * i] = xa[i] - xb[7 - i];
+        cd[0][2 * i + 1] = xb[i] + xa[7 - i];
+        cd[1][2 * i + 1] = xb[i] - xa[7 - i];
+    }
+    const R k0[4] = {kt[m0], kt[N8 - m0], kt[N8 + m0], kt[N4 - m0]};
+    const R k1[2] = {kt[2 * m0], kt[N4 - 2 * m0]};
+    const R k2 = kt[4 * m0];
+    const int pm = pad(m0);
+    sfor<0, 2>([&](auto sc) {
+        constexpr int side = decltype(sc)::value;
+        const cx<R>* v = cd[side];
+        cx<R> l1[2][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bfly<side, R>(v[r], v[7 - r], k0[r], l1[0][r], l1[1][r]);
+        cx<R> l2[4][2];
+        sfor<0, 2>([&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            constexpr int sg = side ^ (SW ? par(P) : 0);
+#pragma unroll
+            for (int r = 0; r < 2; ++r) bfly<sg, R>(l1[P][r], l1[P][3 - r], k1[r], l2[2 * P][r], l2[2 * P + 1][r]);
+        });
+        sfor<0, 4>([&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            constexpr int sg = side ^ (SW ? par(P) : 0);
+            constexpr int h0 = side ^ (SW ? par(2 * P) : 0);
+            constexpr int h1 = side ^ (SW ? par(2 * P + 1) : 0);
+            cx<R> lo, hi;
+            bfly<sg, R>(l2[P][0], l2[P][1], k2, lo, hi);
+            stc(w + h0 * G::HS + G::W3P * (2 * P) + pm, lo);  // depth-3 row 2P, slot m0
+            stc(w + h1 * G::HS + G::W3P * (2 * P + 1) + pm, hi);
+        });
+    });
+}
+
+// chain value c (E_{D-2}(0..8), then D_{D-2}(1..7)): first pad slot of depth-3 row c & 7
+template <int LOGN>
+__device__ __forceinline__ int chslot(int c) {
+    using G = kgeo<LOGN>;
+    return (c >> 3) * G::HS + (c & 7) * G::W3P + 16;
+}
+
+// multiples of N/16: blocks of 4, 2, 1 points and the chain to dct[16] / dst[16]
+template <int V, int LOGN, typename R>
+__device__ __forceinline__ void f1_chain(cx<R>* w, const R* kt, const cx<R> (&raw)[16], bool conj_in) {
+    constexpr int D = LOGN - 2;
+    cx<R> xs[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xs[k] = conj_in ? cconj(raw[k]) : raw[k];
+    cx<R> c[8], d[8];
+    c[0] = xs[0];
+    d[0] = zero<R>();
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        c[k] = xs[k] + xs[16 - k];
+        d[k] = xs[k] - xs[16 - k];
+    }
+    const cx<R> cN2 = xs[8];
+    {
+        cx<R> b8[4] = {c[1], c[3], c[5], c[7]}, b9[2] = {c[2], c[6]};
+        leaf::ot<V, 4, 0, R>(b8, kt, D);
+        leaf::ot<V, 2, 0, R>(b9, kt, D);
+        const cx<R> e0 = c[0] + cN2, e1 = c[0] - cN2;
+        const cx<R> O10 = c[4];
+        const cx<R> E10[3] = {e0 + O10, e1, e0 - O10};
+        const cx<R> E9[5] = {E10[0] + b9[0], E10[1] + b9[1], E10[2], E10[1] - b9[1], E10[0] - b9[0]};
+        cx<R> E8[9];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) E8[k] = E9[k] + b8[k];
+        E8[4] = E9[4];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) E8[8 - k] = E9[k] - b8[k];
+        E8[8] = E9[0] - b8[0];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) stc(w + chslot<LOGN>(k), E8[k]);
+    }
+    {
+        cx<R> b8[4] = {d[1], d[3], d[5], d[7]}, b9[2] = {d[2], d[6]};
+        leaf::ot<V, 4, 1, R>(b8, kt, D);
+        leaf::ot<V, 2, 1, R>(b9, kt, D);
+        const cx<R> E10 = d[4];
+        const cx<R> E9[4] = {zero<R>(), b9[0] + E10, b9[1], b9[0] - E10};
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            stc(w + chslot<LOGN>(8 + k), b8[k - 1] + E9[k]);
+            stc(w + chslot<LOGN>(16 - k), b8[k - 1] - E9[k]);
+        }
+        stc(w + chslot<LOGN>(12), b8[3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// middle orbit pass K
+// ---------------------------------------------------------------------------
+template <int LOGN, int K>
+struct mpass {
+    using G = kgeo<LOGN>;
+    static constexpr int l0 = G::lk(K), r = G::rk(K), W = G::Wk(K), GL = G::Gk(K);
+    static constexpr int WP = W + W / 16, GP = GL + GL / 16;
+    static constexpr int NROW = 1 << l0;
+    static constexpr int PERHALF = G::SPW * NROW * GL;
+    static constexpr int IT = 16 >> r;
+    static constexpr int NV = 1 << r;
+};
+
+struct task {
+    int h, s, P, m;
+};
+
+template <int LOGN, int K>
+__device__ __forceinline__ task mtask(int it, int tid) {
+    using M = mpass<LOGN, K>;
+    const int L = it * kgeo<LOGN>::WG + tid;
+    task t;
+    t.h = L / M::PERHALF;
+    const int rem = L - t.h * M::PERHALF;
+    t.s = rem / (M::NROW * M::GL);
+    const int rem2 = rem - t.s * (M::NROW * M::GL);
+    t.P = rem2 / M::GL;
+    t.m = rem2 - t.P * M::GL;
+    return t;
+}
+
+template <int V, int LOGN, int K, int H, typename R>
+__device__ __forceinline__ void orbit_compute(cx<R>* ws, const R* kf, const cx<R> (&v)[mpass<LOGN, K>::NV], int P,
+                                              int m0) {
+    using G = kgeo<LOGN>;
+    using M = mpass<LOGN, K>;
+    constexpr bool SW = variant_traits<V>::switches;
+    constexpr int NV = M::NV, r = M::r;
+    const R* kw = kf + G::kfbase(K) + (m0 - 1);
+    cx<R> cur[NV][NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) cur[0][e] = v[e];
+    sfor<0, r>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        constexpr int KK = NV >> t;
+        constexpr int rows = 1 << t;
+        cx<R> nxt[NV][NV];
+        sfor<0, rows>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int sg = H ^ (SW ? par(q) : 0);
+#pragma unroll
+            for (int rho = 0; rho < KK / 2; ++rho)
+                bfly<sg, R>(cur[q][rho], cur[q][KK - 1 - rho], kw[G::kft(K, t) + (M::GL - 1) * rho], nxt[2 * q][rho],
+                            nxt[2 * q + 1][rho]);
+        });
+#pragma unroll
+        for (int q = 0; q < 2 * rows; ++q)
+#pragma unroll
+            for (int rho = 0; rho < KK / 2; ++rho) cur[q][rho] = nxt[q][rho];
+    });
+    const int pm = pad(m0);
+    sfor<0, NV>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int hq = H ^ (SW ? par(q) : 0);
+        stc(ws + hq * G::HS + (P * NV + q) * M::GP + pm, cur[q][0]);  // child row P 2^r + q, slot m0
+    });
+}
+
+template <int V, int LOGN, int K, typename R>
+__device__ __forceinline__ void orbit_pass(cx<R>* wall, const R* kt, const R* kf, int tid) {
+    using G = kgeo<LOGN>;
+    using M = mpass<LOGN, K>;
+    constexpr int NV = M::NV, IT = M::IT;
+    cx<R> v[IT][NV];
+    task tk[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        tk[it] = mtask<LOGN, K>(it, tid);
+        const cx<R>* base = wall + tk[it].s * G::SL + tk[it].h * G::HS + tk[it].P * M::WP;
+        const int m = tk[it].m;
+        if (m > 0) {
+            const int pa = pad(m), pb = m + ((m + 15) >> 4);
+#pragma unroll
+            for (int i = 0; i < NV / 2; ++i) {
+                v[it][2 * i] = ldc(base + pa + 2 * M::GP * i);              // slot m + 2 G i
+                v[it][2 * i + 1] = ldc(base + 2 * M::GP * (i + 1) - pb);   // slot 2 G (i+1) - m
+            }
+        } else {
+#pragma unroll
+            for (int e = 1; e < NV; ++e) v[it][e - 1] = ldc(base + e * M::GP);  // slot e G
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const task t = tk[it];
+        cx<R>* ws = wall + t.s * G::SL;
+        if (t.m > 0) {
+            if (t.h == 0) orbit_compute<V, LOGN, K, 0, R>(ws, kf, v[it], t.P, t.m);
+            else orbit_compute<V, LOGN, K, 1, R>(ws, kf, v[it], t.P, t.m);
+        } else {
+            cx<R> o[NV];
+            if (t.h == 0) rowk<V, 0, M::r, R>(v[it], o, kt, G::D);
+            else rowk<V, 1, M::r, R>(v[it], o, kt, G::D);
+            // first pad slot of child rows 1 .. 2^r - 1
+            cx<R>* pb = ws + t.h * G::HS + t.P * M::WP + 16;
+#pragma unroll
+            for (int i = 0; i < NV - 1; ++i) stc(pb + 17 * (i + 1) * (M::GL / 16), o[i]);
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// P3: rows of 16 at depth D-3
+// ---------------------------------------------------------------------------
+template <int V, int LOGN, typename R>
+__device__ __forceinline__ void p3_pass(cx<R>* wall, const R* kt, int tid) {
+    using G = kgeo<LOGN>;
+    constexpr int NR = 1 << (G::D - 3);
+    const int h = tid / (G::SPW * NR);
+    const int rem = tid - h * (G::SPW * NR);
+    const int s = rem / NR, R7 = rem - s * NR;
+    cx<R>* row = wall + s * G::SL + h * G::HS + 17 * R7;
+    cx<R> in[15], o[15];
+#pragma unroll
+    for (int e = 0; e < 15; ++e) in[e] = ldc(row + e + 1);
+    if (h == 0) rowk<V, 0, 4, R>(in, o, kt, G::D);
+    else rowk<V, 1, 4, R>(in, o, kt, G::D);
+#pragma unroll
+    for (int e = 0; e < 15; ++e) stc(row + e + 1, o[e]);
+    __syncthreads();
+}
+
+// offsets (relative to the row's base) of index j-1, j, j+1 of a sub-block of
+// sp values of block a inside a row of depth l1 = l0 + r of pass K
+template <int LOGN, int K>
+__device__ __forceinline__ void child_offsets(int a, int j, int sp, int (&off)[3]) {
+    using G = kgeo<LOGN>;
+    using M = mpass<LOGN, K>;
+    if constexpr (K == G::NP - 1) {
+        // P3 rows: block of sp points at 1 + 16 - 2 sp
+        const int pos = 17 - 2 * sp + j;
+        off[0] = pad(pos - 1);
+        off[1] = pad(pos);
+        off[2] = pad(pos + 1);
+    } else {
+        using M1 = mpass<LOGN, K + 1>;
+        constexpr int r1 = M1::r, G1 = M1::GL;
+        if (sp >= (1 << r1)) {
+            const int pos = (1 << r1) + (M::GL - (M::GL >> a)) + j;  // main array of the child row
+            off[0] = pad(pos - 1);
+            off[1] = pad(pos);
+            off[2] = pad(pos + 1);
+        } else {
+            const int e = (1 << r1) - 2 * sp + j;  // finished by pass K+1: pad slots
+            off[0] = 17 * (e * (G1 / 16)) + 16;
+            off[1] = 17 * ((e + 1) * (G1 / 16)) + 16;
+            off[2] = 17 * ((e + 2) * (G1 / 16)) + 16;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// B_K: backward levels l0 + r - 1 .. l0 of pass K
+// ---------------------------------------------------------------------------
+template <int V, int LOGN, int K, typename R>
+__device__ __forceinline__ void bpass(cx<R>* wall, int tid) {
+    using G = kgeo<LOGN>;
+    using M = mpass<LOGN, K>;
+    constexpr bool SW = variant_traits<V>::switches;
+    constexpr int NV = M::NV, IT = M::IT, LG = ilog2c(M::GL);
+    cx<R> ext[IT][NV][3];
+    task tk[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        tk[it] = mtask<LOGN, K>(it, tid);
+        const task t = tk[it];
+        if (t.m > 0) {
+            const int wm = t.m - 1;
+            const int a = __clz(~(wm << (32 - LG)));  // leading ones of wm in LG bits
+            const int j = wm - (M::GL - (M::GL >> a));
+            const int sp = M::GL >> (a + 1);         // sub-block size of block a at depth l0 + r
+            int off[3];
+            child_offsets<LOGN, K>(a, j, sp, off);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const int hq = t.h ^ (SW ? par(q) : 0);
+                const cx<R>* row = wall + t.s * G::SL + hq * G::HS + (t.P * NV + q) * M::GP;
+                const cx<R> lm = ldc(row + off[0]), lp = ldc(row + off[2]);
+                ext[it][q][0] = j >= 1 ? lm : zero<R>();
+                ext[it][q][1] = ldc(row + off[1]);
+                ext[it][q][2] = j + 1 < sp ? lp : zero<R>();
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const task t = tk[it];
+        if (t.m > 0) {
+            cx<R> o[NV];
+            if (t.h == 0) bwd_run<V, 0, M::r, R>(ext[it], o);
+            else bwd_run<V, 1, M::r, R>(ext[it], o);
+            cx<R>* dst = wall + t.s * G::SL + t.h * G::HS + t.P * M::WP + pad(NV * t.m);  // main array at 2^r m
+#pragma unroll
+            for (int e = 0; e < NV; ++e) stc(dst + e, o[e]);
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// B0: levels 2..0, both sides; thread = position p in the depth-3 layout
+// ---------------------------------------------------------------------------
+template <int V, int LOGN, typename R>
+__device__ __forceinline__ void b0_pass(cx<R>* wall, int tid) {
+    using G = kgeo<LOGN>;
+    constexpr bool SW = variant_traits<V>::switches;
+    constexpr int LW3 = ilog2c(G::W3);
+    const int s = tid / G::T, p = tid - s * G::T;
+    int a = 0, j = 0, sp = 1;
+    int off[3] = {0, 0, 0};
+    if constexpr (G::NP == 0) {
+        // depth 3 = P3 rows: [8 | 4 | 2 | 1] at slots 1..15
+        const int e = p - 1;
+        const int b = e < 8 ? 0 : e < 12 ? 1 : e < 14 ? 2 : 3;
+        sp = 8 >> b;
+        j = e - (16 - 2 * sp);
+        a = b;
+        off[0] = pad(p - 1);
+        off[1] = pad(p);
+        off[2] = pad(p + 1);
+    } else {
+        using M0 = mpass<LOGN, 0>;
+        constexpr int r0 = M0::r, G0 = M0::GL;
+        if (p < (1 << r0)) {
+            const int e = p - 1;  // finished by pass 0: pad slots
+            const int b = __clz(~(e << (32 - r0)));
+            sp = (1 << (r0 - 1)) >> b;
+            j = e - ((1 << r0) - 2 * sp);
+            a = LW3 - r0 + b;  // block whose depth-3 sub-block has sp points
+            off[0] = 17 * (e * (G0 / 16)) + 16;
+            off[1] = 17 * ((e + 1) * (G0 / 16)) + 16;
+            off[2] = 17 * ((e + 2) * (G0 / 16)) + 16;
+        } else {
+            const int pp = p - (1 << r0);
+            a = __clz(~(pp << (32 - LW3)));
+            j = pp - (G::W3 - (G::W3 >> a));
+            sp = G::W3 >> (a + 1);
+            off[0] = pad(p - 1);
+            off[1] = pad(p);
+            off[2] = pad(p + 1);
+        }
+    }
+    const bool act = p > 0;
+    cx<R> ext[2][8][3];
+    if (act) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int hq = side ^ (SW ? par(q) : 0);
+                const cx<R>* row = wall + s * G::SL + hq * G::HS + q * G::W3P;
+                const cx<R> lm = ldc(row + off[0]), lp = ldc(row + off[2]);
+                ext[side][q][0] = j >= 1 ? lm : zero<R>();
+                ext[side][q][1] = ldc(row + off[1]);
+                ext[side][q][2] = j + 1 < sp ? lp : zero<R>();
+            }
+    }
+    __syncthreads();
+    if (act) {
+        const int ob = pad(G::H - (G::H >> a) + 8 * j);  // block a at H - H / 2^a at depth 0
+        cx<R>* ws = wall + s * G::SL;
+        cx<R> o[8];
+        bwd_run<V, 0, 3, R>(ext[0], o);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) stc(ws + ob + e, o[e]);
+        bwd_run<V, 1, 3, R>(ext[1], o);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) stc(ws + G::HS + ob + e, o[e]);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// C0: chain and D_c.  res[] comes out in the order of the thread's F1 orbit:
+// res[j] = X(k0 + (N/8) j), res[8 + j] = X((N/8)(j+1) - k0), j = 0..7, or for
+// k0 = 0, res[i] = X((N/16) i): the same 16 indices the thread loads in F1.
+// ---------------------------------------------------------------------------
+template <int LOGN, typename R>
+__device__ __forceinline__ void c0_compute(const cx<R>* w, int k0, cx<R> (&res)[16]) {
+    using G = kgeo<LOGN>;
+    constexpr int N = G::N, H = G::H, Q = G::Q, D = G::D, N8 = N / 8, N4 = N / 4, N16 = N / 16;
+    constexpr int NW = D - 5;  // walk levels a = 3 .. D-3
+    auto bo = [](int a) { return H - (H >> a) + ((H - (H >> a)) >> 4); };  // pad(base of block a)
+    // X(k) = C(k) - i D(k), X(N-k) = C(k) + i D(k)
+    auto lo = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re + Dv.im, Cv.im - Dv.re}; };
+    auto hi = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re - Dv.im, Cv.im + Dv.re}; };
+    if (k0 > 0) {
+        int ic[NW > 0 ? NW : 1], is[NW > 0 ? NW : 1];
+        R wc[NW > 0 ? NW : 1], wsg[NW > 0 ? NW : 1];
+        int kc = k0;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const int q = Q >> (3 + t);
+            const bool lt = kc < q, gt = kc > q;
+            kc = gt ? 2 * q - kc : kc;
+            ic[t] = kc;
+            wc[t] = lt ? R(1) : gt ? R(-1) : R(0);
+        }
+        int ks = k0;
+        R sgn = R(1);
+        bool done = false;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const int q = Q >> (3 + t);
+            const bool gt = ks > q, eq = ks == q;
+            const int kn = gt ? 2 * q - ks : ks;
+            is[t] = done ? 1 : kn;
+            wsg[t] = done ? R(0) : sgn;
+            sgn = (!done && gt) ? -sgn : sgn;
+            done = done || eq;
+            ks = kn;
+        }
+        const int e8 = done ? 0 : ks;
+        const R wd = done ? R(0) : sgn;
+        cx<R> accs = ldc(w + chslot<LOGN>(8 + e8)) * wd;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const cx<R> o = ldc(w + G::HS + bo(3 + t) + pad(is[t] - 1));
+            accs = cx<R>{accs.re + wsg[t] * o.re, accs.im + wsg[t] * o.im};
+        }
+        cx<R> accc = ldc(w + chslot<LOGN>(kc));
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const cx<R> o = ldc(w + bo(3 + t) + pad(ic[t]));
+            accc = cx<R>{accc.re + wc[t] * o.re, accc.im + wc[t] * o.im};
+        }
+        const int kA = k0, kB = N8 - k0;
+        constexpr int N8P = N8 + N8 / 16;
+        const int pA = pad(kA), pB = pad(kB), pC = pA + N8P, pD = pB + N8P;
+        const int qA = pad(kA - 1), qB = pad(kB - 1), qC = qA + N8P, qD = qB + N8P;
+        const cx<R> Ec3 = accc, Es3 = accs;
+        const cx<R> oc2 = ldc(w + bo(2) + pA);
+        const cx<R> c2a = Ec3 + oc2, c2b = Ec3 - oc2;
+        const cx<R> o1a = ldc(w + bo(1) + pA), o1b = ldc(w + bo(1) + pB);
+        const cx<R> c1[4] = {c2a + o1a, c2b + o1b, c2b - o1b, c2a - o1a};
+        const int pk[4] = {pA, pB, pC, pD}, qk[4] = {qA, qB, qC, qD};
+        cx<R> C[8];  // E_0 at kA, kB, kC, kD, H-kD, H-kC, H-kB, H-kA
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const cx<R> o0 = ldc(w + pk[i]);
+            C[i] = c1[i] + o0;
+            C[7 - i] = c1[i] - o0;
+        }
+        const cx<R> os2 = ldc(w + G::HS + bo(2) + qA);
+        const cx<R> s2a = os2 + Es3, s2b = os2 - Es3;
+        const cx<R> p1a = ldc(w + G::HS + bo(1) + qA), p1b = ldc(w + G::HS + bo(1) + qB);
+        const cx<R> s1[4] = {p1a + s2a, p1b + s2b, p1b - s2b, p1a - s2a};
+        cx<R> Dd[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const cx<R> o0 = ldc(w + G::HS + qk[i]);
+            Dd[i] = o0 + s1[i];
+            Dd[7 - i] = o0 - s1[i];
+        }
+        // harmonics kA, kB, kC, kD, H-kD, H-kC, H-kB, H-kA and N minus them, in
+        // orbit order (both branches write res[0..15] in increasing order)
+        res[0] = lo(C[0], Dd[0]);
+        res[1] = lo(C[2], Dd[2]);
+        res[2] = lo(C[4], Dd[4]);
+        res[3] = lo(C[6], Dd[6]);
+        res[4] = hi(C[7], Dd[7]);
+        res[5] = hi(C[5], Dd[5]);
+        res[6] = hi(C[3], Dd[3]);
+        res[7] = hi(C[1], Dd[1]);
+        res[8] = lo(C[1], Dd[1]);
+        res[9] = lo(C[3], Dd[3]);
+        res[10] = lo(C[5], Dd[5]);
+        res[11] = lo(C[7], Dd[7]);
+        res[12] = hi(C[6], Dd[6]);
+        res[13] = hi(C[4], Dd[4]);
+        res[14] = hi(C[2], Dd[2]);
+        res[15] = hi(C[0], Dd[0]);
+    } else {
+        auto Oc = [&](int a, int k) { return ldc(w + pad(H - (H >> a) + k)); };
+        auto Os = [&](int a, int k) { return ldc(w + G::HS + pad(H - (H >> a) + k - 1)); };
+        // harmonics N16 i: E_3(0) and E_3(N16) (the top harmonic of periodization 32 q_3)
+        cx<R> sum47 = zero<R>();
+#pragma unroll
+        for (int a = 4; a <= D - 3; ++a) sum47 = sum47 + Oc(a, 0);
+        const cx<R> e8_0 = ldc(w + chslot<LOGN>(0));
+        const cx<R> o3 = Oc(3, 0);
+        const cx<R> E3_0 = e8_0 + sum47 + o3;
+        const cx<R> E3_h = e8_0 + sum47 - o3;
+        const cx<R> o2 = Oc(2, 0);
+        const cx<R> E2_0 = E3_0 + o2, E2_2 = E3_0 - o2, E2_1 = E3_h;
+        const cx<R> o1_0 = Oc(1, 0), o1_1 = Oc(1, N16);
+        const cx<R> E1_0 = E2_0 + o1_0, E1_4 = E2_0 - o1_0;
+        const cx<R> E1_1 = E2_1 + o1_1, E1_3 = E2_1 - o1_1, E1_2 = E2_2;
+        cx<R> C[9];
+        const cx<R> E1v[4] = {E1_0, E1_1, E1_2, E1_3};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const cx<R> o0 = Oc(0, N16 * i);
+            C[i] = E1v[i] + o0;
+            C[8 - i] = E1v[i] - o0;
+        }
+        C[4] = E1_4;
+        const cx<R> D2_1 = Os(2, N16);
+        const cx<R> p1 = Os(1, N16);
+        const cx<R> D1v[4] = {zero<R>(), p1 + D2_1, Os(1, 2 * N16), p1 - D2_1};
+        cx<R> Dd[9];
+        Dd[0] = zero<R>();
+        Dd[8] = zero<R>();
+#pragma unroll
+        for (int i = 1; i < 4; ++i) {
+            const cx<R> o0 = Os(0, N16 * i);
+            Dd[i] = o0 + D1v[i];
+            Dd[8 - i] = o0 - D1v[i];
+        }
+        Dd[4] = Os(0, 4 * N16);
+        res[0] = C[0];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) res[i] = lo(C[i], Dd[i]);
+        res[8] = C[8];
+#pragma unroll
+        for (int i = 9; i < 16; ++i) res[i] = hi(C[16 - i], Dd[16 - i]);
+    }
+}
+
+// store the 16 values of a thread at its orbit indices (the F1 load pattern)
+template <int LOGN, typename S, typename R>
+__device__ __forceinline__ void c0_store(S* y, int k0, const cx<R> (&res)[16], bool conj_out) {
+    constexpr int N8 = (1 << LOGN) / 8, N16 = (1 << LOGN) / 16;
+    auto c = [&](cx<R> v) { return conj_out ? cconj(v) : v; };
+    if (k0 > 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            storage<S>::st(y + k0 + N8 * j, c(res[j]));
+            storage<S>::st(y + N8 * (j + 1) - k0, c(res[8 + j]));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) storage<S>::st(y + N16 * i, c(res[i]));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the kernel
+// ---------------------------------------------------------------------------
+template <int V, int LOGN, typename R>
+__device__ __forceinline__ void fill_constants(R* kt, R* kf, const R* __restrict__ ktab, int kshift, bool onthefly,
+                                               int tid) {
+    using G = kgeo<LOGN>;
+    auto kval = [&](int p) -> R {
+        if (p == G::Q / 2) return cos_pi_4<R>();
+        if (!onthefly) return ktab[(long)p << kshift];
+        const double a = (double)p * 2.0 / (double)G::N;
+        constexpr int fam = const_family(V);
+        const double d = fam == 1 ? 1.0 / (2.0 * cospi(a)) : 1.0 / (2.0 * sinpi(a));
+        return p == 0 ? R(0) : R(d);
+    };
+    for (int p = tid; p < G::Q; p += G::WG) kt[p] = kval(p);
+    sfor<0, G::NP>([&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        using M = mpass<LOGN, K>;
+        for (int e = tid; e < G::kfsize(K); e += G::WG) {
+            // e = kft(t) + (GL-1) rho + (m-1)
+            int t = 0;
+#pragma unroll
+            for (int tt = 1; tt < M::r; ++tt)
+                if (e >= G::kft(K, tt)) t = tt;
+            const int e1 = e - ((M::GL - 1) * ((1 << M::r) - (1 << (M::r - t))));
+            const int rho = e1 / (M::GL - 1);
+            const int m = e1 - rho * (M::GL - 1) + 1;
+            const int mr = (rho & 1) ? M::GL * (rho + 1) - m : m + M::GL * rho;
+            kf[G::kfbase(K) + e] = kval(mr << (M::l0 + t));
+        }
+    });
+}
+
+template <int V, typename S, int LOGN>
+__global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_kernel(const S* __restrict__ in, S* __restrict__ out,
+                                                                   const typename storage<S>::R* __restrict__ ktab,
+                                                                   long long batch, int kshift, int flags,
+                                                                   const long long* __restrict__ offsets) {
+    using R = typename storage<S>::R;
+    using G = kgeo<LOGN>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    R* kt = reinterpret_cast<R*>(smem);
+    R* kf = kt + G::Q;
+    cx<R>* wall = reinterpret_cast<cx<R>*>(smem + (G::Q + G::KF_ALLOC) * sizeof(R));
+    const bool conj_in = flags & 1, conj_out = flags & 2, onthefly = flags & 4;
+    const int tid = threadIdx.x;
+    const int fs = tid / G::T, m0 = tid - fs * G::T;  // signal of this thread in F1 / B0 / C0, orbit index
+    const long long gs = (long long)blockIdx.x * G::SPW + fs;
+    const bool live = gs < batch;
+    const long long base = !live ? 0 : offsets ? offsets[gs] : gs * (long long)G::N;
+
+    cx<R> raw[16];
+    f1_load<LOGN, S, R>(in + base, m0, live, raw);
+    fill_constants<V, LOGN, R>(kt, kf, ktab, kshift, onthefly, tid);
+    __syncthreads();
+
+    cx<R>* w = wall + fs * G::SL;
+    if (m0 > 0) f1_orbit<V, LOGN, R>(w, kt, raw, m0, conj_in);
+    else f1_chain<V, LOGN, R>(w, kt, raw, conj_in);
+    __syncthreads();
+
+    sfor<0, G::NP>([&](auto kc) { orbit_pass<V, LOGN, decltype(kc)::value, R>(wall, kt, kf, tid); });
+    p3_pass<V, LOGN, R>(wall, kt, tid);
+    sfor<0, G::NP>([&](auto kc) { bpass<V, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, tid); });
+    b0_pass<V, LOGN, R>(wall, tid);
+    if (live) {
+        cx<R> res[16];
+        c0_compute<LOGN, R>(w, m0, res);
+        c0_store<LOGN, S, R>(out + base, m0, res, conj_out);
+    }
+}
+
+// Fused loss and gradient: y = F x, loss = sum_k |W(k) y(k)|^2 per signal,
+// grad = F^H (2 |W|^2 y) = conj(F conj(g)).  The forward transform's C0
+// leaves each thread with y at exactly the 16 indices its F1 of the second
+// transform needs, so the weighting happens in registers between the two.
+template <typename R, int LOGN>
+constexpr size_t kA_loss_lds_bytes() {
+    using G = kgeo<LOGN>;
+    return (size_t)(G::Q + G::KF_ALLOC + 16) * sizeof(R) + (size_t)G::SPW * G::SL * sizeof(cx<R>);
+}
+
+template <int V, typename S, int LOGN>
+__global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_loss_kernel(const S* __restrict__ xin,
+                                                                        const S* __restrict__ win,
+                                                                        S* __restrict__ grad,
+                                                                        typename storage<S>::R* __restrict__ loss,
+                                                                        const typename storage<S>::R* __restrict__ ktab,
+                                                                        long long batch, int kshift, int flags) {
+    using R = typename storage<S>::R;
+    using G = kgeo<LOGN>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    R* kt = reinterpret_cast<R*>(smem);
+    R* kf = kt + G::Q;
+    R* red = kf + G::KF_ALLOC;  // per-wave partial losses
+    cx<R>* wall = reinterpret_cast<cx<R>*>(smem + (G::Q + G::KF_ALLOC + 16) * sizeof(R));
+    const bool onthefly = flags & 4;
+    const int tid = threadIdx.x;
+    const int fs = tid / G::T, m0 = tid - fs * G::T;
+    const long long gs = (long long)blockIdx.x * G::SPW + fs;
+    const bool live = gs < batch;
+    const long long base = live ? gs * (long long)G::N : 0;
+    cx<R>* w = wall + fs * G::SL;
+
+    cx<R> raw[16];
+    f1_load<LOGN, S, R>(xin + base, m0, live, raw);
+    fill_constants<V, LOGN, R>(kt, kf, ktab, kshift, onthefly, tid);
+    __syncthreads();
+
+    // forward transform
+    if (m0 > 0) f1_orbit<V, LOGN, R>(w, kt, raw, m0, false);
+    else f1_chain<V, LOGN, R>(w, kt, raw, false);
+    __syncthreads();
+    sfor<0, G::NP>([&](auto kc) { orbit_pass<V, LOGN, decltype(kc)::value, R>(wall, kt, kf, tid); });
+    p3_pass<V, LOGN, R>(wall, kt, tid);
+    sfor<0, G::NP>([&](auto kc) { bpass<V, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, tid); });
+    b0_pass<V, LOGN, R>(wall, tid);
+    cx<R> y[16];
+    c0_compute<LOGN, R>(w, m0, y);
+
+    // weighting: g = 2 |W|^2 y at the thread's 16 indices; loss partial
+    cx<R> wt[16];
+    f1_load<LOGN, S, R>(win + base, m0, live, wt);
+    R part = R(0);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const R m2 = wt[i].re * wt[i].re + wt[i].im * wt[i].im;
+        part += m2 * (y[i].re * y[i].re + y[i].im * y[i].im);
+        raw[i] = y[i] * (R(2) * m2);
+    }
+    // per-signal loss, reduced in a fixed order
+    constexpr int GRP = G::T < 64 ? G::T : 64;
+#pragma unroll
+    for (int o = 1; o < GRP; o <<= 1) part += __shfl_xor(part, o);
+    if constexpr (G::T <= 64) {
+        if (m0 == 0 && live) loss[gs] = part;
+    } else {
+        if ((tid & 63) == 0) red[tid >> 6] = part;
+    }
+    __syncthreads();  // C0's LDS reads (and the partials) are complete
+    if constexpr (G::T > 64) {
+        if (m0 == 0 && live) {
+            R sum = R(0);
+            for (int u = 0; u < G::T / 64; ++u) sum += red[fs * (G::T / 64) + u];
+            loss[gs] = sum;
+        }
+    }
+
+    // adjoint: grad = conj(F conj(g))
+    if (m0 > 0) f1_orbit<V, LOGN, R>(w, kt, raw, m0, true);
+    else f1_chain<V, LOGN, R>(w, kt, raw, true);
+    __syncthreads();
+    sfor<0, G::NP>([&](auto kc) { orbit_pass<V, LOGN, decltype(kc)::value, R>(wall, kt, kf, tid); });
+    p3_pass<V, LOGN, R>(wall, kt, tid);
+    sfor<0, G::NP>([&](auto kc) { bpass<V, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, tid); });
+    b0_pass<V, LOGN, R>(wall, tid);
+    if (live) {
+        c0_compute<LOGN, R>(w, m0, y);
+        c0_store<LOGN, S, R>(grad + base, m0, y, true);
+    }
+}
+
+template <int V, typename S, int LOGN>
+hipError_t launch_kA_loss_n(const loss_launch& a, hipStream_t st) {
+    using R = typename storage<S>::R;
+    using G = kgeo<LOGN>;
+    const long long grid = (a.batch + G::SPW - 1) / G::SPW;
+    const size_t lds = kA_loss_lds_bytes<R, LOGN>();
+    hipLaunchKernelGGL((amqft_kA_loss_kernel<V, S, LOGN>), dim3((unsigned)grid), dim3(G::WG), lds, st,
+                       static_cast<const S*>(a.x), static_cast<const S*>(a.w), static_cast<S*>(a.grad),
+                       static_cast<R*>(a.loss), static_cast<const R*>(a.ktab), (long long)a.batch,
+                       a.ktab_log2n - LOGN, a.onthefly ? 4 : 0);
+    return hipGetLastError();
+}
+
+template <int V, typename S>
+hipError_t launch_kA_loss_s(const loss_launch& a, hipStream_t st) {
+    switch (a.logn) {
+    case 8: return launch_kA_loss_n<V, S, 8>(a, st);
+    case 9: return launch_kA_loss_n<V, S, 9>(a, st);
+    case 10: return launch_kA_loss_n<V, S, 10>(a, st);
+    case 11: return launch_kA_loss_n<V, S, 11>(a, st);
+    case 12: return launch_kA_loss_n<V, S, 12>(a, st);
+    case 13: return launch_kA_loss_n<V, S, 13>(a, st);
+    default: return launch_kA_loss_n<V, S, 14>(a, st);
+    }
+}
+
+template <int V, typename S, int LOGN>
+hipError_t prime_kA_loss_n() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kA_loss_kernel<V, S, LOGN>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if constexpr (LOGN < 14) {
+        if (e == hipSuccess) e = prime_kA_loss_n<V, S, LOGN + 1>();
+    }
+    return e;
+}
+
+template <int V, typename S, int LOGN>
+hipError_t launch_kA_n(const lds_launch& a, hipStream_t st) {
+    using R = typename storage<S>::R;
+    using G = kgeo<LOGN>;
+    const int flags = (a.conj_in ? 1 : 0) | (a.conj_out ? 2 : 0) | (a.onthefly ? 4 : 0);
+    const long long grid = (a.batch + G::SPW - 1) / G::SPW;
+    const size_t lds = kA_lds_bytes<R, LOGN>();
+    hipLaunchKernelGGL((amqft_kA_kernel<V, S, LOGN>), dim3((unsigned)grid), dim3(G::WG), lds, st,
+                       static_cast<const S*>(a.in), static_cast<S*>(a.out), static_cast<const R*>(a.ktab),
+                       (long long)a.batch, a.ktab_log2n - LOGN, flags, static_cast<const long long*>(a.offsets));
+    return hipGetLastError();
+}
+
+template <int V, typename S>
+hipError_t launch_kA_s(const lds_launch& a, hipStream_t st) {
+    switch (a.logn) {
+    case 8: return launch_kA_n<V, S, 8>(a, st);
+    case 9: return launch_kA_n<V, S, 9>(a, st);
+    case 10: return launch_kA_n<V, S, 10>(a, st);
+    case 11: return launch_kA_n<V, S, 11>(a, st);
+    case 12: return launch_kA_n<V, S, 12>(a, st);
+    case 13: return launch_kA_n<V, S, 13>(a, st);
+    default: return launch_kA_n<V, S, 14>(a, st);
+    }
+}
+
+template <int V, typename S, int LOGN>
+hipError_t prime_kA_n() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kA_kernel<V, S, LOGN>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if constexpr (LOGN < 14) {
+        if (e == hipSuccess) e = prime_kA_n<V, S, LOGN + 1>();
+    }
+    return e;
+}
+
+}  // namespace
+
+bool kA_supported(int variant, int logn, int dtype) {
+    if (variant != 4 && variant != 8) return false;
+    if (dtype == 1) return logn >= 8 && logn <= 14;
+    if (dtype == 0) return logn >= 8 && logn <= 13;
+    return false;
+}
+
+void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes) {
+    const int N = 1 << logn, T = N / 16, WG = T >= 256 ? T : 256;
+    *threads = WG;
+    *signals_per_wg = WG / T;
+    size_t b = 0;
+    switch (logn) {
+    case 8: b = dtype == 0 ? kA_lds_bytes<double, 8>() : kA_lds_bytes<float, 8>(); break;
+    case 9: b = dtype == 0 ? kA_lds_bytes<double, 9>() : kA_lds_bytes<float, 9>(); break;
+    case 10: b = dtype == 0 ? kA_lds_bytes<double, 10>() : kA_lds_bytes<float, 10>(); break;
+    case 11: b = dtype == 0 ? kA_lds_bytes<double, 11>() : kA_lds_bytes<float, 11>(); break;
+    case 12: b = dtype == 0 ? kA_lds_bytes<double, 12>() : kA_lds_bytes<float, 12>(); break;
+    case 13: b = dtype == 0 ? kA_lds_bytes<double, 13>() : kA_lds_bytes<float, 13>(); break;
+    default: b = dtype == 0 ? kA_lds_bytes<double, 14>() : kA_lds_bytes<float, 14>(); break;
+    }
+    *lds_bytes = b;
+}
+
+hipError_t prime_kA(int variant, int dtype) {
+    hipError_t e = hipSuccess;
+    if (variant == 4) {
+        e = dtype == 0 ? prime_kA_n<4, double2, 8>() : prime_kA_n<4, float2, 8>();
+        if (e == hipSuccess) e = dtype == 0 ? prime_kA_loss_n<4, double2, 8>() : prime_kA_loss_n<4, float2, 8>();
+    } else if (variant == 8) {
+        e = dtype == 0 ? prime_kA_n<8, double2, 8>() : prime_kA_n<8, float2, 8>();
+        if (e == hipSuccess) e = dtype == 0 ? prime_kA_loss_n<8, double2, 8>() : prime_kA_loss_n<8, float2, 8>();
+    }
+    return e;
+}
+
+bool kA_loss_supported(int variant, int logn, int dtype) { return kA_supported(variant, logn, dtype); }
+
+hipError_t launch_kA_loss(const loss_launch& a, hipStream_t st) {
+    if (a.batch <= 0) return hipSuccess;
+    if (a.variant == 4) return a.dtype == 0 ? launch_kA_loss_s<4, double2>(a, st) : launch_kA_loss_s<4, float2>(a, st);
+    return a.dtype == 0 ? launch_kA_loss_s<8, double2>(a, st) : launch_kA_loss_s<8, float2>(a, st);
+}
+
+hipError_t launch_kA(const lds_launch& a, hipStream_t st) {
+    if (a.batch <= 0) return hipSuccess;
+    if (a.variant == 4) return a.dtype == 0 ? launch_kA_s<4, double2>(a, st) : launch_kA_s<4, float2>(a, st);
+    return a.dtype == 0 ? launch_kA_s<8, double2>(a, st) : launch_kA_s<8, float2>(a, st);
+}
+
+}  // namespace amqft

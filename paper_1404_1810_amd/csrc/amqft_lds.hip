@@ -300,6 +300,7 @@ static hipError_t launch_loss_v(const loss_launch& a, hipStream_t s) {
 }
 
 hipError_t launch_loss(const loss_launch& a, hipStream_t s) {
+    if (kA_loss_supported(a.variant, a.logn, a.dtype)) return launch_kA_loss(a, s);
     switch (a.variant) {
     case 1: return launch_loss_v<1>(a, s);
     case 2: return launch_loss_v<2>(a, s);
@@ -402,7 +403,7 @@ static hipError_t prime_v(int dtype) {
 
 hipError_t prime_lds(int variant, int dtype) {
     hipError_t e = prime_fast(variant, dtype);
-    if (e == hipSuccess) e = prime_a4096(variant, dtype);
+    if (e == hipSuccess) e = prime_kA(variant, dtype);
     if (e != hipSuccess) return e;
     switch (variant) {
     case 1: return prime_v<1>(dtype);
@@ -421,10 +422,10 @@ void describe_lds(const lds_launch& a, char* buf, size_t len) {
     const char* sname = st[a.dtype & 3];
     int threads = 0, spw = 1;
     size_t lds = 0;
-    if (!a.generic && a4096_supported(a.variant, a.logn, a.dtype)) {
-        a4096_shape(a.dtype, &threads, &lds);
-        snprintf(buf, len, "amqft_a4096_kernel<%d, %s> grid=%lld block=%d lds=%zu", a.variant, sname,
-                 (long long)a.batch, threads, lds);
+    if (!a.generic && kA_supported(a.variant, a.logn, a.dtype)) {
+        kA_shape(a.logn, a.dtype, &threads, &spw, &lds);
+        snprintf(buf, len, "amqft_kA_kernel<%d, %s, %d> grid=%lld block=%d lds=%zu", a.variant, sname, a.logn,
+                 (long long)((a.batch + spw - 1) / spw), threads, lds);
     } else if (!a.generic && fast_supported(a.logn, a.dtype)) {
         fast_shape(a.logn, a.dtype, &threads, &spw, &lds);
         snprintf(buf, len, "amqft_fast_kernel<%d, %s, %d> grid=%lld block=%d lds=%zu", a.variant, sname, a.logn,
@@ -439,7 +440,7 @@ void describe_lds(const lds_launch& a, char* buf, size_t len) {
 }
 
 hipError_t launch_lds(const lds_launch& a, hipStream_t s) {
-    if (!a.generic && a4096_supported(a.variant, a.logn, a.dtype)) return launch_a4096(a, s);
+    if (!a.generic && kA_supported(a.variant, a.logn, a.dtype)) return launch_kA(a, s);
     if (!a.generic && fast_supported(a.logn, a.dtype)) return launch_fast(a, s);
     switch (a.variant) {
     case 1: return launch_v<1>(a, s);
