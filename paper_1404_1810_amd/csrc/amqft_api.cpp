@@ -54,6 +54,7 @@ struct amqft_plan_s {
     int device = 0;
     // multi-pass (signals larger than LDS)
     bool multipass = false;
+    bool large = false;  // the four-kernel path of amqft_kA.hip (uses ws[0..2] and chunk)
     int sb = 0;
     int64_t chunk = 0;
     void* ws[3] = {nullptr, nullptr, nullptr};
@@ -139,6 +140,7 @@ amqft_status build_constants(amqft_plan_s* p, int log2n) {
 amqft_status prime(int variant, int dtype) {
     hipError_t e = prime_lds(variant, dtype);
     if (e == hipSuccess) e = prime_multipass(variant, dtype);
+    if (e == hipSuccess) e = prime_kL(variant, dtype);
     return e == hipSuccess ? AMQFT_OK : hip_fail(e);
 }
 
@@ -195,6 +197,25 @@ void tune_put(const std::string& key, int v) {
 
 amqft_status exec_single(amqft_plan p, const void* in, void* out, hipStream_t stream, bool adjoint) {
     if (p->batch == 0) return AMQFT_OK;
+    if (p->large) {
+        kl_launch k{};
+        k.variant = p->variant;
+        k.dtype = p->dtype;
+        k.logn = p->logn;
+        k.batch = p->batch;
+        k.chunk = p->chunk;
+        k.in = in;
+        k.out = out;
+        k.ws1 = p->ws[0];
+        k.ws2 = p->ws[1];
+        k.wsc = p->ws[2];
+        k.ktab = p->ktab;
+        k.conj_in = adjoint;
+        k.conj_out = adjoint;
+        k.offsets = p->offsets;
+        hipError_t e = launch_kL(k, stream);
+        return e == hipSuccess ? AMQFT_OK : hip_fail(e);
+    }
     if (p->multipass) {
         mp_launch m{};
         m.variant = p->variant;
@@ -386,7 +407,19 @@ amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int varian
     amqft_status st = build_constants(p, logn);
     if (st == AMQFT_OK) st = prime(variant, dtype);
     if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
-    if (mp) {
+    if (mp && !(flags & AMQFT_FLAG_FORCE_MULTIPASS) && kL_supported(variant, logn, dtype)) {
+        // workspaces sized so that both stay within the last-level cache
+        p->large = true;
+        const size_t per = kL_ws_bytes_per_signal(logn, dtype);
+        const size_t cap = size_t(64) << 20;  // bytes per workspace buffer
+        p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per)));
+        const size_t chain = (size_t)p->chunk * 16 * (dtype == AMQFT_C128 ? 16 : 8);
+        p->ws_bytes = 2 * (size_t)p->chunk * per + chain;
+        for (int i = 0; i < 3 && batch > 0; ++i) {
+            e = hipMalloc(&p->ws[i], i < 2 ? (size_t)p->chunk * per : chain);
+            if (e != hipSuccess) { p->ws[i] = nullptr; amqft_plan_destroy(p); return hip_fail(e); }
+        }
+    } else if (mp) {
         p->multipass = true;
         // forced (test) plans use small sub-blocks so that several global levels run
         p->sb = (flags & AMQFT_FLAG_FORCE_MULTIPASS) ? std::max(2, std::min(multipass_sb(dtype), logn - 5))
@@ -550,7 +583,7 @@ amqft_status amqft_power_loss_grad(amqft_plan p, const void* x, const void* w, v
     if (p->many) return AMQFT_ERR_UNSUPPORTED;
     if (p->batch == 0) return AMQFT_OK;
     if (!x || !w || !grad || !loss) return AMQFT_ERR_INVALID_ARG;
-    if (p->logn < 2 || p->multipass) return AMQFT_ERR_UNSUPPORTED;
+    if (p->logn < 2 || p->multipass || p->large) return AMQFT_ERR_UNSUPPORTED;
     loss_launch a{};
     a.variant = p->variant;
     a.dtype = p->dtype;
@@ -637,6 +670,9 @@ amqft_status amqft_plan_describe(amqft_plan p, char* buf, size_t len) {
         for (auto& c : p->classes) nclass += c.sub ? 1 : 0;
         snprintf(buf, len, "many-length plan: %lld signals, persistent kernel grid=%d items=%d, %d long-length classes",
                  (long long)p->count, p->grid, p->nitems, nclass);
+    } else if (p->large) {
+        snprintf(buf, len, "amqft_kL_{top,rows,back,chain}<%d> n=%lld chunk=%lld", p->variant, (long long)p->n,
+                 (long long)p->chunk);
     } else if (p->multipass) {
         snprintf(buf, len, "multi-pass engine n=%lld sb=%d chunk=%lld", (long long)p->n, p->sb, (long long)p->chunk);
     } else {

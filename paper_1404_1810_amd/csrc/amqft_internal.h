@@ -74,6 +74,26 @@ bool kA_supported(int variant, int logn, int dtype);
 hipError_t launch_kA(const lds_launch& a, hipStream_t stream);
 hipError_t prime_kA(int variant, int dtype);
 void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
+// N = 2^15 .. 2^17 (FP64 to 2^16), variants 4 and 8: four kernels over a
+// global workspace (top levels, rows through the kA kernels, back levels,
+// chain); signals run in chunks of `chunk`.
+struct kl_launch {
+    int variant, dtype, logn;
+    int64_t batch, chunk;
+    const void* in;
+    void* out;
+    void* ws1;  // chunk * N complex values of the arithmetic type
+    void* ws2;  // chunk * N
+    void* wsc;  // chunk * 16
+    const void* ktab;  // table built for exactly N
+    int conj_in, conj_out;
+    const void* offsets = nullptr;
+};
+bool kL_supported(int variant, int logn, int dtype);
+size_t kL_ws_bytes_per_signal(int logn, int dtype);
+hipError_t prime_kL(int variant, int dtype);
+hipError_t launch_kL(const kl_launch& a, hipStream_t stream);
+
 // fused loss / gradient on the same kernels (forward, weighting, adjoint)
 bool kA_loss_supported(int variant, int logn, int dtype);
 

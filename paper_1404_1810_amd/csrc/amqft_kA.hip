@@ -202,29 +202,16 @@ __device__ __forceinline__ void f1_load(const S* x, int m0, bool live, cx<R> (&r
     }
 }
 
-template <int V, int LOGN, typename R>
-__device__ __forceinline__ void f1_orbit(cx<R>* w, const R* kt, const cx<R> (&raw)[16], int m0, bool conj_in) {
-    using G = kgeo<LOGN>;
+// levels 0..2 on an orbit of 8 slots of two sides (cd[s][r], slots m_{2i} =
+// m0 + (N/8) i, m_{2i+1} = (N/8)(i+1) - m0); put(s, P, v) receives the value
+// of depth-3 row P of side s at slot m0.  kt: constant table of length N.
+template <int V, int LOGN, typename R, typename PUT>
+__device__ __forceinline__ void f1_levels(const R* kt, cx<R> (&cd)[2][8], int m0, PUT&& put) {
     constexpr bool SW = variant_traits<V>::switches;
-    constexpr int N8 = G::N / 8, N4 = G::N / 4;
-    cx<R> xa[8], xb[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        xa[j] = conj_in ? cconj(raw[j]) : raw[j];
-        xb[j] = conj_in ? cconj(raw[8 + j]) : raw[8 + j];
-    }
-    cx<R> cd[2][8];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        cd[0][2 * i] = xa[i] + xb[7 - i];
-        cd[1][2 * i] = xa[i] - xb[7 - i];
-        cd[0][2 * i + 1] = xb[i] + xa[7 - i];
-        cd[1][2 * i + 1] = xb[i] - xa[7 - i];
-    }
+    constexpr int N8 = (1 << LOGN) / 8, N4 = (1 << LOGN) / 4;
     const R k0[4] = {kt[m0], kt[N8 - m0], kt[N8 + m0], kt[N4 - m0]};
     const R k1[2] = {kt[2 * m0], kt[N4 - 2 * m0]};
     const R k2 = kt[4 * m0];
-    const int pm = pad(m0);
     sfor<0, 2>([&](auto sc) {
         constexpr int side = decltype(sc)::value;
         const cx<R>* v = cd[side];
@@ -241,13 +228,45 @@ __device__ __forceinline__ void f1_orbit(cx<R>* w, const R* kt, const cx<R> (&ra
         sfor<0, 4>([&](auto pc) {
             constexpr int P = decltype(pc)::value;
             constexpr int sg = side ^ (SW ? par(P) : 0);
-            constexpr int h0 = side ^ (SW ? par(2 * P) : 0);
-            constexpr int h1 = side ^ (SW ? par(2 * P + 1) : 0);
             cx<R> lo, hi;
             bfly<sg, R>(l2[P][0], l2[P][1], k2, lo, hi);
-            stc(w + h0 * G::HS + G::W3P * (2 * P) + pm, lo);  // depth-3 row 2P, slot m0
-            stc(w + h1 * G::HS + G::W3P * (2 * P + 1) + pm, hi);
+            put(std::integral_constant<int, side>{}, std::integral_constant<int, 2 * P>{}, lo);
+            put(std::integral_constant<int, side>{}, std::integral_constant<int, 2 * P + 1>{}, hi);
         });
+    });
+}
+
+// D_c / D_r on the orbit: c(m) = x(m) + x(N-m), d(m) = x(m) - x(N-m) at the
+// orbit slots, from the 16 loaded points (raw[j] = x(m0 + (N/8) j),
+// raw[8+j] = x((N/8)(j+1) - m0))
+template <typename R>
+__device__ __forceinline__ void f1_dc(const cx<R> (&raw)[16], bool conj_in, cx<R> (&cd)[2][8]) {
+    cx<R> xa[8], xb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        xa[j] = conj_in ? cconj(raw[j]) : raw[j];
+        xb[j] = conj_in ? cconj(raw[8 + j]) : raw[8 + j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        cd[0][2 * i] = xa[i] + xb[7 - i];
+        cd[1][2 * i] = xa[i] - xb[7 - i];
+        cd[0][2 * i + 1] = xb[i] + xa[7 - i];
+        cd[1][2 * i + 1] = xb[i] - xa[7 - i];
+    }
+}
+
+template <int V, int LOGN, typename R>
+__device__ __forceinline__ void f1_orbit(cx<R>* w, const R* kt, const cx<R> (&raw)[16], int m0, bool conj_in) {
+    using G = kgeo<LOGN>;
+    constexpr bool SW = variant_traits<V>::switches;
+    cx<R> cd[2][8];
+    f1_dc<R>(raw, conj_in, cd);
+    const int pm = pad(m0);
+    f1_levels<V, LOGN, R>(kt, cd, m0, [&](auto sc, auto pc, cx<R> v) {
+        constexpr int side = decltype(sc)::value, P8 = decltype(pc)::value;
+        constexpr int hh = side ^ (SW ? par(P8) : 0);
+        stc(w + hh * G::HS + G::W3P * P8 + pm, v);  // depth-3 row P8, slot m0
     });
 }
 
@@ -259,8 +278,8 @@ __device__ __forceinline__ int chslot(int c) {
 }
 
 // multiples of N/16: blocks of 4, 2, 1 points and the chain to dct[16] / dst[16]
-template <int V, int LOGN, typename R>
-__device__ __forceinline__ void f1_chain(cx<R>* w, const R* kt, const cx<R> (&raw)[16], bool conj_in) {
+template <int V, int LOGN, typename R, typename PUT>
+__device__ __forceinline__ void f1_chain_to(const R* kt, const cx<R> (&raw)[16], bool conj_in, PUT&& put) {
     constexpr int D = LOGN - 2;
     cx<R> xs[16];
 #pragma unroll
@@ -290,7 +309,7 @@ __device__ __forceinline__ void f1_chain(cx<R>* w, const R* kt, const cx<R> (&ra
         for (int k = 1; k < 4; ++k) E8[8 - k] = E9[k] - b8[k];
         E8[8] = E9[0] - b8[0];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) stc(w + chslot<LOGN>(k), E8[k]);
+        for (int k = 0; k < 9; ++k) put(k, E8[k]);
     }
     {
         cx<R> b8[4] = {d[1], d[3], d[5], d[7]}, b9[2] = {d[2], d[6]};
@@ -300,11 +319,16 @@ __device__ __forceinline__ void f1_chain(cx<R>* w, const R* kt, const cx<R> (&ra
         const cx<R> E9[4] = {zero<R>(), b9[0] + E10, b9[1], b9[0] - E10};
 #pragma unroll
         for (int k = 1; k < 4; ++k) {
-            stc(w + chslot<LOGN>(8 + k), b8[k - 1] + E9[k]);
-            stc(w + chslot<LOGN>(16 - k), b8[k - 1] - E9[k]);
+            put(8 + k, b8[k - 1] + E9[k]);
+            put(16 - k, b8[k - 1] - E9[k]);
         }
-        stc(w + chslot<LOGN>(12), b8[3]);
+        put(12, b8[3]);
     }
+}
+
+template <int V, int LOGN, typename R>
+__device__ __forceinline__ void f1_chain(cx<R>* w, const R* kt, const cx<R> (&raw)[16], bool conj_in) {
+    f1_chain_to<V, LOGN, R>(kt, raw, conj_in, [&](int c, cx<R> v) { stc(w + chslot<LOGN>(c), v); });
 }
 
 // ---------------------------------------------------------------------------
@@ -598,12 +622,23 @@ __device__ __forceinline__ void b0_pass(cx<R>* wall, int tid) {
 // res[j] = X(k0 + (N/8) j), res[8 + j] = X((N/8)(j+1) - k0), j = 0..7, or for
 // k0 = 0, res[i] = X((N/16) i): the same 16 indices the thread loads in F1.
 // ---------------------------------------------------------------------------
-template <int LOGN, typename R>
-__device__ __forceinline__ void c0_compute(const cx<R>* w, int k0, cx<R> (&res)[16]) {
+// LDS layout of a signal in the kA kernels: padded halves, chain in pad slots
+template <int LOGN>
+struct lds_layout {
+    using G = kgeo<LOGN>;
+    static constexpr int idx(int k) { return k + (k >> 4); }
+    static constexpr int base(int side, int a) { return side * G::HS + idx(G::H - (G::H >> a)); }
+    static constexpr int chain(int c) { return (c >> 3) * G::HS + (c & 7) * G::W3P + 16; }
+};
+
+template <int LOGN, typename R, typename L>
+__device__ __forceinline__ void c0_compute(const cx<R>* w, const cx<R>* chn, int k0, cx<R> (&res)[16]) {
     using G = kgeo<LOGN>;
     constexpr int N = G::N, H = G::H, Q = G::Q, D = G::D, N8 = N / 8, N4 = N / 4, N16 = N / 16;
     constexpr int NW = D - 5;  // walk levels a = 3 .. D-3
-    auto bo = [](int a) { return H - (H >> a) + ((H - (H >> a)) >> 4); };  // pad(base of block a)
+    // position of harmonic k of block a on a side = L::base(side, a) + L::idx(k)
+    auto bo = [](int a) { return L::base(0, a); };
+    constexpr int HSL = L::base(1, 0);
     // X(k) = C(k) - i D(k), X(N-k) = C(k) + i D(k)
     auto lo = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re + Dv.im, Cv.im - Dv.re}; };
     auto hi = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re - Dv.im, Cv.im + Dv.re}; };
@@ -635,22 +670,22 @@ __device__ __forceinline__ void c0_compute(const cx<R>* w, int k0, cx<R> (&res)[
         }
         const int e8 = done ? 0 : ks;
         const R wd = done ? R(0) : sgn;
-        cx<R> accs = ldc(w + chslot<LOGN>(8 + e8)) * wd;
+        cx<R> accs = ldc(chn + L::chain(8 + e8)) * wd;
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
-            const cx<R> o = ldc(w + G::HS + bo(3 + t) + pad(is[t] - 1));
+            const cx<R> o = ldc(w + HSL + bo(3 + t) + L::idx(is[t] - 1));
             accs = cx<R>{accs.re + wsg[t] * o.re, accs.im + wsg[t] * o.im};
         }
-        cx<R> accc = ldc(w + chslot<LOGN>(kc));
+        cx<R> accc = ldc(chn + L::chain(kc));
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
-            const cx<R> o = ldc(w + bo(3 + t) + pad(ic[t]));
+            const cx<R> o = ldc(w + bo(3 + t) + L::idx(ic[t]));
             accc = cx<R>{accc.re + wc[t] * o.re, accc.im + wc[t] * o.im};
         }
         const int kA = k0, kB = N8 - k0;
-        constexpr int N8P = N8 + N8 / 16;
-        const int pA = pad(kA), pB = pad(kB), pC = pA + N8P, pD = pB + N8P;
-        const int qA = pad(kA - 1), qB = pad(kB - 1), qC = qA + N8P, qD = qB + N8P;
+        constexpr int N8P = L::idx(N8);
+        const int pA = L::idx(kA), pB = L::idx(kB), pC = pA + N8P, pD = pB + N8P;
+        const int qA = L::idx(kA - 1), qB = L::idx(kB - 1), qC = qA + N8P, qD = qB + N8P;
         const cx<R> Ec3 = accc, Es3 = accs;
         const cx<R> oc2 = ldc(w + bo(2) + pA);
         const cx<R> c2a = Ec3 + oc2, c2b = Ec3 - oc2;
@@ -664,14 +699,14 @@ __device__ __forceinline__ void c0_compute(const cx<R>* w, int k0, cx<R> (&res)[
             C[i] = c1[i] + o0;
             C[7 - i] = c1[i] - o0;
         }
-        const cx<R> os2 = ldc(w + G::HS + bo(2) + qA);
+        const cx<R> os2 = ldc(w + HSL + bo(2) + qA);
         const cx<R> s2a = os2 + Es3, s2b = os2 - Es3;
-        const cx<R> p1a = ldc(w + G::HS + bo(1) + qA), p1b = ldc(w + G::HS + bo(1) + qB);
+        const cx<R> p1a = ldc(w + HSL + bo(1) + qA), p1b = ldc(w + HSL + bo(1) + qB);
         const cx<R> s1[4] = {p1a + s2a, p1b + s2b, p1b - s2b, p1a - s2a};
         cx<R> Dd[8];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const cx<R> o0 = ldc(w + G::HS + qk[i]);
+            const cx<R> o0 = ldc(w + HSL + qk[i]);
             Dd[i] = o0 + s1[i];
             Dd[7 - i] = o0 - s1[i];
         }
@@ -694,13 +729,13 @@ __device__ __forceinline__ void c0_compute(const cx<R>* w, int k0, cx<R> (&res)[
         res[14] = hi(C[2], Dd[2]);
         res[15] = hi(C[0], Dd[0]);
     } else {
-        auto Oc = [&](int a, int k) { return ldc(w + pad(H - (H >> a) + k)); };
-        auto Os = [&](int a, int k) { return ldc(w + G::HS + pad(H - (H >> a) + k - 1)); };
+        auto Oc = [&](int a, int k) { return ldc(w + bo(a) + L::idx(k)); };
+        auto Os = [&](int a, int k) { return ldc(w + HSL + bo(a) + L::idx(k - 1)); };
         // harmonics N16 i: E_3(0) and E_3(N16) (the top harmonic of periodization 32 q_3)
         cx<R> sum47 = zero<R>();
 #pragma unroll
         for (int a = 4; a <= D - 3; ++a) sum47 = sum47 + Oc(a, 0);
-        const cx<R> e8_0 = ldc(w + chslot<LOGN>(0));
+        const cx<R> e8_0 = ldc(chn + L::chain(0));
         const cx<R> o3 = Oc(3, 0);
         const cx<R> E3_0 = e8_0 + sum47 + o3;
         const cx<R> E3_h = e8_0 + sum47 - o3;
@@ -825,7 +860,7 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_kernel(const S* __res
     b0_pass<V, LOGN, R>(wall, tid);
     if (live) {
         cx<R> res[16];
-        c0_compute<LOGN, R>(w, m0, res);
+        c0_compute<LOGN, R, lds_layout<LOGN>>(w, w, m0, res);
         c0_store<LOGN, S, R>(out + base, m0, res, conj_out);
     }
 }
@@ -876,7 +911,7 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_loss_kernel(const S* 
     sfor<0, G::NP>([&](auto kc) { bpass<V, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, tid); });
     b0_pass<V, LOGN, R>(wall, tid);
     cx<R> y[16];
-    c0_compute<LOGN, R>(w, m0, y);
+    c0_compute<LOGN, R, lds_layout<LOGN>>(w, w, m0, y);
 
     // weighting: g = 2 |W|^2 y at the thread's 16 indices; loss partial
     cx<R> wt[16];
@@ -915,7 +950,7 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_loss_kernel(const S* 
     sfor<0, G::NP>([&](auto kc) { bpass<V, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, tid); });
     b0_pass<V, LOGN, R>(wall, tid);
     if (live) {
-        c0_compute<LOGN, R>(w, m0, y);
+        c0_compute<LOGN, R, lds_layout<LOGN>>(w, w, m0, y);
         c0_store<LOGN, S, R>(grad + base, m0, y, true);
     }
 }
@@ -992,6 +1027,214 @@ hipError_t prime_kA_n() {
     return e;
 }
 
+// ---------------------------------------------------------------------------
+// Signals larger than one workgroup's LDS (N = 2^15 .. 2^17): four kernels
+// over a global workspace.  A depth-3 row of an N-point transform (W3 = N/16
+// slots) is one side of the dct_ot / dst_ot recursion of an N/8-point
+// transform, with the constant table subsampled by 8, so the row pass runs
+// the kernels above at log2 N - 3.
+//   top    D_c / D_r + levels 0..2 (F1): depth-3 rows -> ws1, chain -> wsc
+//   rows   two rows (one per context) per workgroup through every level
+//          below depth 3 and back; each row -> ws1 in block layout (block a
+//          at W3 - W3 / 2^a)
+//   back   levels 2..0 for every block (B0 over global rows) -> ws2, depth 0
+//          in block layout per side (block a at H - H / 2^a)
+//   chain  chain, D_c and the store (C0 over ws2 and wsc)
+// ---------------------------------------------------------------------------
+template <int LOGN>
+struct global_layout {
+    static constexpr int H = (1 << LOGN) / 2;
+    static constexpr int idx(int k) { return k; }
+    static constexpr int base(int side, int a) { return side * H + H - (H >> a); }
+    static constexpr int chain(int c) { return c; }
+};
+
+template <int V, typename S, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_top(const S* __restrict__ in, cx<typename storage<S>::R>* __restrict__ ws1,
+                                                     cx<typename storage<S>::R>* __restrict__ wsc,
+                                                     const typename storage<S>::R* __restrict__ ktab, long long sig0,
+                                                     long long batch, int flags, const long long* __restrict__ offsets) {
+    using R = typename storage<S>::R;
+    constexpr int N = 1 << LOGN, W3 = N / 16;
+    const int m0 = blockIdx.x * 256 + threadIdx.x;
+    const long long sl = blockIdx.y, gs = sig0 + sl;
+    if (gs >= batch || m0 >= W3) return;
+    const bool conj_in = flags & 1;
+    const long long base = offsets ? offsets[gs] : gs * (long long)N;
+    cx<R> raw[16];
+    f1_load<LOGN, S, R>(in + base, m0, true, raw);
+    cx<R>* rows = ws1 + sl * N;
+    if (m0 > 0) {
+        cx<R> cd[2][8];
+        f1_dc<R>(raw, conj_in, cd);
+        f1_levels<V, LOGN, R>(ktab, cd, m0, [&](auto sc, auto pc, cx<R> v) {
+            constexpr int side = decltype(sc)::value, P8 = decltype(pc)::value;
+            rows[(side * 8 + P8) * W3 + m0] = v;  // depth-3 row (side, P8), slot m0
+        });
+    } else {
+        f1_chain_to<V, LOGN, R>(ktab, raw, conj_in, [&](int c, cx<R> v) { wsc[sl * 16 + c] = v; });
+    }
+}
+
+template <int V, typename R, int LOGN>
+__global__ __launch_bounds__(kgeo<LOGN - 3>::WG) void amqft_kL_rows(cx<R>* __restrict__ ws1, const R* __restrict__ ktab) {
+    constexpr int LR = LOGN - 3;  // rows = sides of a 2^LR-point transform
+    using G = kgeo<LR>;
+    constexpr bool SW = variant_traits<V>::switches;
+    constexpr int W3 = (1 << LOGN) / 16;  // = G::H
+    constexpr int N8r = G::N / 8;
+    extern __shared__ __align__(16) unsigned char smem[];
+    R* kt = reinterpret_cast<R*>(smem);
+    R* kf = kt + G::Q;
+    cx<R>* wall = reinterpret_cast<cx<R>*>(smem + (G::Q + G::KF_ALLOC) * sizeof(R));
+    const int tid = threadIdx.x;
+    const int P = blockIdx.x;  // depth-3 path; rows (0, P) and (1, P)
+    cx<R>* sig = ws1 + (long long)blockIdx.y * (1 << LOGN);
+    // half hh (= context) holds the row of side hh ^ parity(P)
+    cx<R>* row[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) row[hh] = sig + ((hh ^ (SW ? par(P) : 0)) * 8 + P) * W3;
+    const int m0 = tid;
+    cx<R> cd[2][8];
+    if (m0 > 0) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                cd[hh][2 * i] = row[hh][m0 + N8r * i];
+                cd[hh][2 * i + 1] = row[hh][N8r * (i + 1) - m0];
+            }
+    } else {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int k = 1; k < 8; ++k) cd[hh][k] = row[hh][(W3 / 8) * k];
+    }
+    fill_constants<V, LR, R>(kt, kf, ktab, 3, false, tid);
+    __syncthreads();
+    if (m0 > 0) {
+        const int pm = pad(m0);
+        f1_levels<V, LR, R>(kt, cd, m0, [&](auto sc, auto pc, cx<R> v) {
+            constexpr int hh = decltype(sc)::value, P8 = decltype(pc)::value;
+            constexpr int h2 = hh ^ (SW ? par(P8) : 0);
+            stc(wall + h2 * G::HS + G::W3P * P8 + pm, v);
+        });
+    } else {
+        // the row's blocks of 4, 2 and 1 points (slots (W3/8) k), straight to the output layout
+        sfor<0, 2>([&](auto hc) {
+            constexpr int hh = decltype(hc)::value;
+            cx<R> b4[4] = {cd[hh][1], cd[hh][3], cd[hh][5], cd[hh][7]}, b2[2] = {cd[hh][2], cd[hh][6]};
+            leaf::ot<V, 4, hh, R>(b4, kt, G::D);
+            leaf::ot<V, 2, hh, R>(b2, kt, G::D);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) row[hh][W3 - 8 + i] = b4[i];
+            row[hh][W3 - 4] = b2[0];
+            row[hh][W3 - 3] = b2[1];
+            row[hh][W3 - 2] = cd[hh][4];
+        });
+    }
+    __syncthreads();
+    sfor<0, G::NP>([&](auto kc) { orbit_pass<V, LR, decltype(kc)::value, R>(wall, kt, kf, tid); });
+    p3_pass<V, LR, R>(wall, kt, tid);
+    sfor<0, G::NP>([&](auto kc) { bpass<V, LR, G::NP - 1 - decltype(kc)::value, R>(wall, tid); });
+    b0_pass<V, LR, R>(wall, tid);
+    // blocks with at least 8 points: LDS block layout -> the row
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh)
+        for (int pos = tid; pos < W3 - 8; pos += G::WG) row[hh][pos] = ldc(wall + hh * G::HS + pad(pos));
+}
+
+template <int V, typename R, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_back(const cx<R>* __restrict__ ws1, cx<R>* __restrict__ ws2) {
+    constexpr int N = 1 << LOGN, H = N / 2, W3 = N / 16, LW3 = ilog2c(W3);
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= W3 - 1) return;
+    const cx<R>* sig = ws1 + (long long)blockIdx.y * N;
+    const int a = __clz(~(p << (32 - LW3)));  // block of position p in the row's block layout
+    const int j = p - (W3 - (W3 >> a));
+    const int sp = W3 >> (a + 1);
+    const int pm = p > 0 ? p - 1 : 0;
+    cx<R> ext[2][8][3];
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const cx<R>* row = sig + (side * 8 + q) * W3;
+            const cx<R> lm = row[pm], lp = row[p + 1];
+            ext[side][q][0] = j >= 1 ? lm : zero<R>();
+            ext[side][q][1] = row[p];
+            ext[side][q][2] = j + 1 < sp ? lp : zero<R>();
+        }
+    cx<R>* out = ws2 + (long long)blockIdx.y * N + (H - (H >> a)) + 8 * j;
+    cx<R> o[8];
+    bwd_run<V, 0, 3, R>(ext[0], o);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = o[e];
+    bwd_run<V, 1, 3, R>(ext[1], o);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[H + e] = o[e];
+}
+
+template <typename S, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_chain(const cx<typename storage<S>::R>* __restrict__ ws2,
+                                                       const cx<typename storage<S>::R>* __restrict__ wsc,
+                                                       S* __restrict__ out, long long sig0, long long batch, int flags,
+                                                       const long long* __restrict__ offsets) {
+    using R = typename storage<S>::R;
+    constexpr int N = 1 << LOGN, W3 = N / 16;
+    const int k0 = blockIdx.x * 256 + threadIdx.x;
+    const long long sl = blockIdx.y, gs = sig0 + sl;
+    if (gs >= batch || k0 >= W3) return;
+    const long long base = offsets ? offsets[gs] : gs * (long long)N;
+    cx<R> res[16];
+    c0_compute<LOGN, R, global_layout<LOGN>>(ws2 + sl * N, wsc + sl * 16, k0, res);
+    c0_store<LOGN, S, R>(out + base, k0, res, (flags & 2) != 0);
+}
+
+template <int V, typename S, int LOGN>
+hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
+    using R = typename storage<S>::R;
+    using G = kgeo<LOGN - 3>;
+    constexpr int N = 1 << LOGN, W3 = N / 16;
+    const int flags = (a.conj_in ? 1 : 0) | (a.conj_out ? 2 : 0);
+    const size_t lds = kA_lds_bytes<R, LOGN - 3>();
+    cx<R>* ws1 = static_cast<cx<R>*>(a.ws1);
+    cx<R>* ws2 = static_cast<cx<R>*>(a.ws2);
+    cx<R>* wsc = static_cast<cx<R>*>(a.wsc);
+    const R* kt = static_cast<const R*>(a.ktab);
+    for (long long s0 = 0; s0 < a.batch; s0 += a.chunk) {
+        const long long nb = a.batch - s0 < a.chunk ? a.batch - s0 : a.chunk;
+        const dim3 gw((W3 + 255) / 256, (unsigned)nb);
+        hipLaunchKernelGGL((amqft_kL_top<V, S, LOGN>), gw, dim3(256), 0, st, static_cast<const S*>(a.in), ws1, wsc, kt,
+                           s0, (long long)a.batch, flags, static_cast<const long long*>(a.offsets));
+        hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN>), dim3(8, (unsigned)nb), dim3(G::WG), lds, st, ws1, kt);
+        hipLaunchKernelGGL((amqft_kL_back<V, R, LOGN>), gw, dim3(256), 0, st, static_cast<const cx<R>*>(ws1), ws2);
+        hipLaunchKernelGGL((amqft_kL_chain<S, LOGN>), gw, dim3(256), 0, st, static_cast<const cx<R>*>(ws2),
+                           static_cast<const cx<R>*>(wsc), static_cast<S*>(a.out), s0, (long long)a.batch, flags,
+                           static_cast<const long long*>(a.offsets));
+    }
+    return hipGetLastError();
+}
+
+template <int V, typename S>
+hipError_t launch_kL_s(const kl_launch& a, hipStream_t st) {
+    switch (a.logn) {
+    case 15: return launch_kL_n<V, S, 15>(a, st);
+    case 16: return launch_kL_n<V, S, 16>(a, st);
+    default: return launch_kL_n<V, S, 17>(a, st);
+    }
+}
+
+template <int V, typename R, int LOGN>
+hipError_t prime_kL_n() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kL_rows<V, R, LOGN>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if constexpr (LOGN < 17) {
+        if (e == hipSuccess) e = prime_kL_n<V, R, LOGN + 1>();
+    }
+    return e;
+}
+
 }  // namespace
 
 bool kA_supported(int variant, int logn, int dtype) {
@@ -1036,6 +1279,27 @@ hipError_t launch_kA_loss(const loss_launch& a, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
     if (a.variant == 4) return a.dtype == 0 ? launch_kA_loss_s<4, double2>(a, st) : launch_kA_loss_s<4, float2>(a, st);
     return a.dtype == 0 ? launch_kA_loss_s<8, double2>(a, st) : launch_kA_loss_s<8, float2>(a, st);
+}
+
+bool kL_supported(int variant, int logn, int dtype) {
+    if (variant != 4 && variant != 8) return false;
+    if (dtype == 1) return logn >= 15 && logn <= 17;
+    if (dtype == 0) return logn >= 15 && logn <= 16;
+    return false;
+}
+
+size_t kL_ws_bytes_per_signal(int logn, int dtype) { return ((size_t)1 << logn) * (dtype == 0 ? 16 : 8); }
+
+hipError_t prime_kL(int variant, int dtype) {
+    if (variant == 4) return dtype == 0 ? prime_kL_n<4, double, 15>() : prime_kL_n<4, float, 15>();
+    if (variant == 8) return dtype == 0 ? prime_kL_n<8, double, 15>() : prime_kL_n<8, float, 15>();
+    return hipSuccess;
+}
+
+hipError_t launch_kL(const kl_launch& a, hipStream_t st) {
+    if (a.batch <= 0) return hipSuccess;
+    if (a.variant == 4) return a.dtype == 0 ? launch_kL_s<4, double2>(a, st) : launch_kL_s<4, float2>(a, st);
+    return a.dtype == 0 ? launch_kL_s<8, double2>(a, st) : launch_kL_s<8, float2>(a, st);
 }
 
 hipError_t launch_kA(const lds_launch& a, hipStream_t st) {
