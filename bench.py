@@ -379,9 +379,12 @@ def bench_precision(args, stream):
     n = 1 << 20
     B = args.batch if args.batch != 16384 else 1024
     xh = torch.empty((B, n, 2), dtype=torch.float16, device="cuda")
+    t0 = time.time()
     for s0 in range(0, B, 8):
         m = min(8, B - s0)
         xh[s0:s0 + m].copy_(torch.from_numpy(inputs.cfg_fp16_rows(m, n, start=s0)))
+        if (s0 // 8) % 32 == 31:
+            log("precision inputs: %d of %d signals resident (%.0f s)" % (s0 + m, B, time.time() - t0))
     yh = torch.empty_like(xh)
     sample = [0, B // 2, B - 1][: min(3, B)]
     xs = xh[sample].float().cpu().numpy()

@@ -74,6 +74,13 @@ enum {
     AMQFT_FLAG_FORCE_MULTIPASS = 4u
 };
 
+/* Environment (read at plan creation):
+ *   AMQFT_TUNE_CACHE   path of a JSON-lines file that keeps autotuned launch
+ *                      shapes across processes (see amqft_plan_create_many);
+ *   AMQFT_LARGE_WS_MB  size in MiB of each of the two workspace buffers of
+ *                      plans for N above one workgroup's LDS (default 128;
+ *                      signals run in chunks that fit them). */
+
 /* Largest supported log2(N). */
 #define AMQFT_MAX_LOG2N 24
 

@@ -411,7 +411,11 @@ amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int varian
         // workspaces sized so that both stay within the last-level cache
         p->large = true;
         const size_t per = kL_ws_bytes_per_signal(logn, dtype);
-        const size_t cap = size_t(64) << 20;  // bytes per workspace buffer
+        size_t cap = size_t(128) << 20;  // bytes per workspace buffer
+        if (const char* env = getenv("AMQFT_LARGE_WS_MB")) {
+            const long mb = atol(env);
+            if (mb >= 1 && mb <= 8192) cap = size_t(mb) << 20;
+        }
         p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per)));
         const size_t chain = (size_t)p->chunk * 16 * (dtype == AMQFT_C128 ? 16 : 8);
         p->ws_bytes = 2 * (size_t)p->chunk * per + chain;
