@@ -154,3 +154,41 @@ def test_multipass_large(variant):
         b = bound(variant, dtype == "c128", x, ref)
         if np.isfinite(b):
             assert e <= b, (dtype, n, e, b)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", [4, 8])
+def test_large_path(variant, monkeypatch):
+    """The four-kernel path for N above one workgroup's LDS (variants 4 and 8:
+    2^15 .. 2^17 FP32, 2^15 .. 2^16 FP64), its workspaces cut to 1 MiB so that
+    every batch runs in several chunks with a ragged last one; forward with the
+    table and with on-the-fly constants, adjoint, in place."""
+    api = _api()
+    from paper_1404_1810_amd import _lib
+    monkeypatch.setenv("AMQFT_LARGE_WS_MB", "1")
+    cases = (("c64", 1 << 15, 5, 4), ("c64", 1 << 17, 3, 1), ("c128", 1 << 15, 3, 2), ("c128", 1 << 16, 2, 1))
+    for dtype, n, batch, chunk in cases:
+        _say("large path", dtype, "variant", variant, "n", n, "batch", batch)
+        x_np = inputs.complex_normal(5000 + n, batch, n)
+        if dtype == "c64":
+            x_np = x_np.astype(np.complex64)
+        ref = truth(x_np, 4)
+        b = bound(variant, dtype == "c128", x_np, ref)
+        tdt = torch.complex128 if dtype == "c128" else torch.complex64
+        x = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
+        for flags in (0, _lib.FLAG_ONTHEFLY_CONSTANTS):
+            plan = api.Plan(n, batch, variant, _lib.C128 if dtype == "c128" else _lib.C64, flags)
+            d = plan.describe()
+            assert "amqft_kL" in d and ("chunk=%d" % chunk) in d, d
+            y = plan.exec(x)
+            torch.cuda.synchronize()
+            e = rel(y.cpu().numpy(), ref)
+            assert e <= b, (dtype, n, flags, e, b)
+            if flags == 0:
+                g = x.clone()
+                plan.exec(g, out=g, adjoint=True)  # in place
+                torch.cuda.synchronize()
+                ea = rel(g.cpu().numpy(), np.conj(truth(np.conj(x_np), 4)))
+                assert ea <= b, (dtype, n, "adjoint", ea, b)
+            plan.close()
+        assert x.dtype == tdt
