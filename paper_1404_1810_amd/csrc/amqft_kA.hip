@@ -1239,9 +1239,8 @@ hipError_t prime_kL_n() {
 
 bool kA_supported(int variant, int logn, int dtype) {
     if (variant != 4 && variant != 8) return false;
-    if (dtype == 1) return logn >= 8 && logn <= 14;
     if (dtype == 0) return logn >= 8 && logn <= 13;
-    return false;
+    return logn >= 8 && logn <= 14;  // FP32 arithmetic: FP32, FP16 and BF16 storage
 }
 
 void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes) {
@@ -1261,19 +1260,31 @@ void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* ld
     *lds_bytes = b;
 }
 
-hipError_t prime_kA(int variant, int dtype) {
-    hipError_t e = hipSuccess;
-    if (variant == 4) {
-        e = dtype == 0 ? prime_kA_n<4, double2, 8>() : prime_kA_n<4, float2, 8>();
-        if (e == hipSuccess) e = dtype == 0 ? prime_kA_loss_n<4, double2, 8>() : prime_kA_loss_n<4, float2, 8>();
-    } else if (variant == 8) {
-        e = dtype == 0 ? prime_kA_n<8, double2, 8>() : prime_kA_n<8, float2, 8>();
-        if (e == hipSuccess) e = dtype == 0 ? prime_kA_loss_n<8, double2, 8>() : prime_kA_loss_n<8, float2, 8>();
+template <int V>
+static hipError_t prime_kA_v(int dtype) {
+    switch (dtype) {
+    case 0: {
+        const hipError_t e = prime_kA_n<V, double2, 8>();
+        return e == hipSuccess ? prime_kA_loss_n<V, double2, 8>() : e;
     }
-    return e;
+    case 1: {
+        const hipError_t e = prime_kA_n<V, float2, 8>();
+        return e == hipSuccess ? prime_kA_loss_n<V, float2, 8>() : e;
+    }
+    case 2: return prime_kA_n<V, __half2, 8>();
+    default: return prime_kA_n<V, bf16x2, 8>();
+    }
 }
 
-bool kA_loss_supported(int variant, int logn, int dtype) { return kA_supported(variant, logn, dtype); }
+hipError_t prime_kA(int variant, int dtype) {
+    if (variant == 4) return prime_kA_v<4>(dtype);
+    if (variant == 8) return prime_kA_v<8>(dtype);
+    return hipSuccess;
+}
+
+bool kA_loss_supported(int variant, int logn, int dtype) {
+    return (dtype == 0 || dtype == 1) && kA_supported(variant, logn, dtype);
+}
 
 hipError_t launch_kA_loss(const loss_launch& a, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
@@ -1283,29 +1294,48 @@ hipError_t launch_kA_loss(const loss_launch& a, hipStream_t st) {
 
 bool kL_supported(int variant, int logn, int dtype) {
     if (variant != 4 && variant != 8) return false;
-    if (dtype == 1) return logn >= 15 && logn <= 17;
     if (dtype == 0) return logn >= 15 && logn <= 16;
-    return false;
+    return logn >= 15 && logn <= 17;  // FP32 arithmetic: FP32, FP16 and BF16 storage
 }
 
 size_t kL_ws_bytes_per_signal(int logn, int dtype) { return ((size_t)1 << logn) * (dtype == 0 ? 16 : 8); }
 
 hipError_t prime_kL(int variant, int dtype) {
     if (variant == 4) return dtype == 0 ? prime_kL_n<4, double, 15>() : prime_kL_n<4, float, 15>();
-    if (variant == 8) return dtype == 0 ? prime_kL_n<8, double, 15>() : prime_kL_n<8, float, 15>();
+    if (variant == 8) return dtype == 0 ? prime_kL_n<8, double, 15>() : prime_kL_n<8, float, 15>();  // R = float for 1..3
     return hipSuccess;
+}
+
+template <int V>
+static hipError_t launch_kL_t(const kl_launch& a, hipStream_t st) {
+    switch (a.dtype) {
+    case 0: return launch_kL_s<V, double2>(a, st);
+    case 1: return launch_kL_s<V, float2>(a, st);
+    case 2: return launch_kL_s<V, __half2>(a, st);
+    default: return launch_kL_s<V, bf16x2>(a, st);
+    }
 }
 
 hipError_t launch_kL(const kl_launch& a, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
-    if (a.variant == 4) return a.dtype == 0 ? launch_kL_s<4, double2>(a, st) : launch_kL_s<4, float2>(a, st);
-    return a.dtype == 0 ? launch_kL_s<8, double2>(a, st) : launch_kL_s<8, float2>(a, st);
+    if (a.variant == 4) return launch_kL_t<4>(a, st);
+    return launch_kL_t<8>(a, st);
+}
+
+template <int V>
+static hipError_t launch_kA_t(const lds_launch& a, hipStream_t st) {
+    switch (a.dtype) {
+    case 0: return launch_kA_s<V, double2>(a, st);
+    case 1: return launch_kA_s<V, float2>(a, st);
+    case 2: return launch_kA_s<V, __half2>(a, st);
+    default: return launch_kA_s<V, bf16x2>(a, st);
+    }
 }
 
 hipError_t launch_kA(const lds_launch& a, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
-    if (a.variant == 4) return a.dtype == 0 ? launch_kA_s<4, double2>(a, st) : launch_kA_s<4, float2>(a, st);
-    return a.dtype == 0 ? launch_kA_s<8, double2>(a, st) : launch_kA_s<8, float2>(a, st);
+    if (a.variant == 4) return launch_kA_t<4>(a, st);
+    return launch_kA_t<8>(a, st);
 }
 
 }  // namespace amqft

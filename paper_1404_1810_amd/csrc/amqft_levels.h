@@ -223,10 +223,41 @@ __device__ void a_bwd_level(cx<R>* w, int ltid, int T, int D, int H, int l, int 
 // totals of the preceding (forward) or following (backward) threads.
 // ---------------------------------------------------------------------------
 template <typename R>
-__device__ cx<R> chunk_carry(cx<R>* scr, int ltid, cx<R> total, bool participates, bool fwd, int threads_per_seg) {
-    scr[ltid] = participates ? total : cx<R>{R(0), R(0)};
+__device__ __forceinline__ cx<R> shfl_up_cx(cx<R> v, int d) {
+    return cx<R>{__shfl_up(v.re, d), __shfl_up(v.im, d)};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> shfl_down_cx(cx<R> v, int d) {
+    return cx<R>{__shfl_down(v.re, d), __shfl_down(v.im, d)};
+}
+
+// max_tps: the largest threads_per_seg of any thread of the workgroup (the
+// same value in every thread).  Segments of at most 64 threads are aligned
+// groups of lanes inside one wave, and their exclusive scan runs on lane
+// shuffles; longer segments go through LDS.  Both forms contain a barrier,
+// which callers use to order their LDS reads before their writes.
+template <typename R>
+__device__ cx<R> chunk_carry(cx<R>* scr, int ltid, cx<R> total, bool participates, bool fwd, int threads_per_seg,
+                             int max_tps = 1 << 30) {
+    const cx<R> z = {R(0), R(0)};
+    if (max_tps <= 64) {
+        const int tps = participates ? threads_per_seg : 1;
+        const int pos = ltid & (tps - 1);
+        const cx<R> own = participates ? total : z;
+        // w_p = t_{p-1} (forward) or t_{p+1} (backward) inside the segment,
+        // then an inclusive Hillis-Steele scan of w over the segment
+        const cx<R> up1 = shfl_up_cx(own, 1), dn1 = shfl_down_cx(own, 1);
+        cx<R> w = fwd ? (pos >= 1 ? up1 : z) : (pos + 1 < tps ? dn1 : z);
+        for (int d = 1; d < max_tps; d <<= 1) {
+            const cx<R> u = fwd ? shfl_up_cx(w, d) : shfl_down_cx(w, d);
+            if (fwd ? pos >= d : pos + d < tps) w = w + u;
+        }
+        __syncthreads();
+        return participates && threads_per_seg > 1 ? w : z;
+    }
+    scr[ltid] = participates ? total : z;
     __syncthreads();
-    cx<R> c = {R(0), R(0)};
+    cx<R> c = z;
     if (participates && threads_per_seg > 1) {
         const int first = ltid & ~(threads_per_seg - 1);
         const int last = first + threads_per_seg - 1;
@@ -313,7 +344,8 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
     const bool long_seg = act0 && hseg > KMAX;
     const bool fwd0 = fwdk[0];
     const cx<R> total = fwd0 ? y[KMAX - 1] : y[0];
-    const cx<R> Yin = chunk_carry(scr, ltid, total, long_seg, fwd0, long_seg ? hseg / KMAX : 1);
+    const int max_tps = ((1 << (D - 1 - l)) / KMAX) > 1 ? (1 << (D - 1 - l)) / KMAX : 1;
+    const cx<R> Yin = chunk_carry(scr, ltid, total, long_seg, fwd0, long_seg ? hseg / KMAX : 1, max_tps);
     if (long_seg) {
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
@@ -615,7 +647,8 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
     const bool long_seg = act0 && hseg > KMAX;
     const bool fwd0 = fwdk[0];
     const cx<R> total = fwd0 ? y[KMAX - 1] : y[0];
-    const cx<R> Yin = chunk_carry(scr, ltid, total, long_seg, fwd0, long_seg ? hseg / KMAX : 1);
+    const int max_tps = ((1 << (D - 1 - l)) / KMAX) > 1 ? (1 << (D - 1 - l)) / KMAX : 1;
+    const cx<R> Yin = chunk_carry(scr, ltid, total, long_seg, fwd0, long_seg ? hseg / KMAX : 1, max_tps);
     if (long_seg) {
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {

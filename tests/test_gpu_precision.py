@@ -86,3 +86,40 @@ def test_fp16_n2p20_sampled(variant):
     _say("  rel err", e)
     if variant <= 4:
         assert e < 5e-4, (variant, e)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", [4, 8])
+def test_reduced_storage_large_path(variant, monkeypatch):
+    """FP16 and BF16 storage on the four-kernel path (N above one workgroup's
+    LDS), workspaces cut to 1 MiB so that the batch runs in chunks."""
+    from paper_1404_1810_amd import _lib, api
+    monkeypatch.setenv("AMQFT_LARGE_WS_MB", "1")
+    for kind, n, batch in (("fp16", 1 << 15, 5), ("bf16", 1 << 17, 2)):
+        _say(kind, "large path variant", variant, "n", n, "batch", batch)
+        z = inputs.complex_uniform(60 + n, batch, n)
+        if kind == "fp16":
+            h = _half_pairs(z)
+            xq = h[..., 0].astype(np.float64) + 1j * h[..., 1].astype(np.float64)
+            xt = torch.from_numpy(h).cuda()
+            dt = _lib.C32H
+        else:
+            bits = inputs.to_bf16_bits(np.stack([z.real, z.imag], axis=-1))
+            xq64 = inputs.from_bf16_bits(bits).astype(np.float64)
+            xq = xq64[..., 0] + 1j * xq64[..., 1]
+            xt = torch.from_numpy(bits.view(np.int16)).cuda().view(torch.bfloat16)
+            dt = _lib.C32B
+        plan = api.Plan(n, batch, variant, dt, 0)
+        assert "amqft_kL" in plan.describe(), plan.describe()
+        y = plan.exec(xt)
+        torch.cuda.synchronize()
+        if kind == "fp16":
+            yn = y.cpu().numpy().astype(np.float64)
+        else:
+            yn = inputs.from_bf16_bits(y.view(torch.int16).cpu().numpy().view(np.uint16)).astype(np.float64)
+        plan.close()
+        yc = yn[..., 0] + 1j * yn[..., 1]
+        e = rel(yc, truth(xq)) if np.all(np.isfinite(yc)) else np.inf
+        _say("  rel err", e)
+        if variant == 4:
+            assert e < (5e-4 if kind == "fp16" else 4e-3), (kind, n, e)
