@@ -393,11 +393,11 @@ def bench_precision(args, stream):
     res = {}
     for v in range(1, 9):
         plan = api.Plan(n, B, v, _lib.C32H, _lib.FLAG_ONTHEFLY_CONSTANTS)
-        r = time_launches(lambda: plan.exec(xh, out=yh), max(3, args.steps // 4), 1, stream)
+        r = time_launches(lambda: plan.exec(xh, out=yh), max(3, min(20, args.steps // 10)), 2, stream)
         got = yh[sample].float().cpu().numpy()
         got = got[..., 0].astype(np.float64) + 1j * got[..., 1].astype(np.float64)
         nonfinite = int((~np.isfinite(got)).sum())
-        res[str(v)] = {"avg_ms": round(r["avg_ms"], 3),
+        res[str(v)] = {"kernel": plan.describe(), "avg_ms": round(r["avg_ms"], 3),
                        "hbm_gbs": round(B * n * 8.0 / r["avg_ms"] / 1e6, 1),
                        "rel_l2_vs_fp64_oracle": _rel(got, ref) if nonfinite == 0 else None,
                        "nonfinite_outputs": nonfinite}

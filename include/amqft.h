@@ -65,8 +65,11 @@ typedef enum {
 
 /* Plan flags. */
 enum {
-    /* Generate the trigonometric constants (Sec. 7.1) on the device in FP64
-     * inside every kernel instead of reading the plan's precomputed table. */
+    /* Generate the trigonometric constants (Sec. 7.1) on the device in FP64,
+     * rounded once to the working precision: the LDS-resident kernels do so
+     * inside every workgroup; for the paths that read constants from global
+     * memory (N above one workgroup's LDS) the plan's table is generated on
+     * the device at plan creation instead of being uploaded from the host. */
     AMQFT_FLAG_ONTHEFLY_CONSTANTS = 1u,
     /* Do not consult the tuning table; use the default launch shape. */
     AMQFT_FLAG_NO_AUTOTUNE = 2u,

@@ -406,6 +406,13 @@ amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int varian
     if (e != hipSuccess) { delete p; return hip_fail(e); }
     amqft_status st = build_constants(p, logn);
     if (st == AMQFT_OK) st = prime(variant, dtype);
+    if (st == AMQFT_OK && (flags & AMQFT_FLAG_ONTHEFLY_CONSTANTS) && logn >= 2) {
+        // the table that kernels read from global memory (the multi-pass and
+        // large-N paths) is generated on the device as well
+        e = fill_table_device(p->ktab, variant, dtype, logn, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) st = hip_fail(e);
+    }
     if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
     if (mp && !(flags & AMQFT_FLAG_FORCE_MULTIPASS) && kL_supported(variant, logn, dtype)) {
         // workspaces sized so that both stay within the last-level cache
@@ -675,7 +682,9 @@ amqft_status amqft_plan_describe(amqft_plan p, char* buf, size_t len) {
         snprintf(buf, len, "many-length plan: %lld signals, persistent kernel grid=%d items=%d, %d long-length classes",
                  (long long)p->count, p->grid, p->nitems, nclass);
     } else if (p->large) {
-        snprintf(buf, len, "amqft_kL_{top,rows,back,chain}<%d> n=%lld chunk=%lld", p->variant, (long long)p->n,
+        snprintf(buf, len, p->logn >= 18 ? "amqft_kL_{top,rtop,rows,rback,back,chain}<%d> n=%lld chunk=%lld"
+                                         : "amqft_kL_{top,rows,back,chain}<%d> n=%lld chunk=%lld",
+                 p->variant, (long long)p->n,
                  (long long)p->chunk);
     } else if (p->multipass) {
         snprintf(buf, len, "multi-pass engine n=%lld sb=%d chunk=%lld", (long long)p->n, p->sb, (long long)p->chunk);

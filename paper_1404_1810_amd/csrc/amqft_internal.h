@@ -128,6 +128,9 @@ size_t multipass_ws_bytes_per_signal(int logn, int dtype);
 // Raise the dynamic-LDS limit of the kernels of a variant/dtype (done at plan
 // creation so that no attribute call happens during graph capture).
 hipError_t prime_lds(int variant, int dtype);
+// Overwrite a plan's constant table (N/4 entries of the arithmetic type,
+// log2 N >= 2) with values generated on the device in FP64.
+hipError_t fill_table_device(void* ktab, int variant, int dtype, int logn, hipStream_t stream);
 hipError_t prime_multipass(int variant, int dtype);
 
 // Bytes of dynamic LDS and threads per workgroup the LDS engine uses.

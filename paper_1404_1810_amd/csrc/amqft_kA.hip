@@ -204,14 +204,15 @@ __device__ __forceinline__ void f1_load(const S* x, int m0, bool live, cx<R> (&r
 
 // levels 0..2 on an orbit of 8 slots of two sides (cd[s][r], slots m_{2i} =
 // m0 + (N/8) i, m_{2i+1} = (N/8)(i+1) - m0); put(s, P, v) receives the value
-// of depth-3 row P of side s at slot m0.  kt: constant table of length N.
-template <int V, int LOGN, typename R, typename PUT>
+// of depth-3 row P of side s at slot m0.  kt: constant table of length N, or
+// (KS > 0) of length 2^KS N, read at stride 2^KS.
+template <int V, int LOGN, typename R, int KS = 0, typename PUT>
 __device__ __forceinline__ void f1_levels(const R* kt, cx<R> (&cd)[2][8], int m0, PUT&& put) {
     constexpr bool SW = variant_traits<V>::switches;
     constexpr int N8 = (1 << LOGN) / 8, N4 = (1 << LOGN) / 4;
-    const R k0[4] = {kt[m0], kt[N8 - m0], kt[N8 + m0], kt[N4 - m0]};
-    const R k1[2] = {kt[2 * m0], kt[N4 - 2 * m0]};
-    const R k2 = kt[4 * m0];
+    const R k0[4] = {kt[m0 << KS], kt[(N8 - m0) << KS], kt[(N8 + m0) << KS], kt[(N4 - m0) << KS]};
+    const R k1[2] = {kt[(2 * m0) << KS], kt[(N4 - 2 * m0) << KS]};
+    const R k2 = kt[(4 * m0) << KS];
     sfor<0, 2>([&](auto sc) {
         constexpr int side = decltype(sc)::value;
         const cx<R>* v = cd[side];
@@ -1028,8 +1029,8 @@ hipError_t prime_kA_n() {
 }
 
 // ---------------------------------------------------------------------------
-// Signals larger than one workgroup's LDS (N = 2^15 .. 2^17): four kernels
-// over a global workspace.  A depth-3 row of an N-point transform (W3 = N/16
+// Signals larger than one workgroup's LDS (N = 2^15 .. 2^20): four kernels
+// over a global workspace (six from 2^18 on, see amqft_kL_rtop / rback).  A depth-3 row of an N-point transform (W3 = N/16
 // slots) is one side of the dct_ot / dst_ot recursion of an N/8-point
 // transform, with the constant table subsampled by 8, so the row pass runs
 // the kernels above at log2 N - 3.
@@ -1076,24 +1077,32 @@ __global__ __launch_bounds__(256) void amqft_kL_top(const S* __restrict__ in, cx
     }
 }
 
-template <int V, typename R, int LOGN>
-__global__ __launch_bounds__(kgeo<LOGN - 3>::WG) void amqft_kL_rows(cx<R>* __restrict__ ws1, const R* __restrict__ ktab) {
-    constexpr int LR = LOGN - 3;  // rows = sides of a 2^LR-point transform
+// Rows at depth DEP (3, or 6 for N >= 2^18): a pair of rows of the two
+// contexts is the pair of sides of a 2^(log2 N - DEP)-point transform.  Depth-3
+// rows live in ws by side (row (side, P) at (8 side + P) W), depth-6 rows by
+// context (row (P, h) at (2 P + h) W); either way the pair leaves in the
+// block layout of the row (block a at W - W / 2^a).
+template <int V, typename R, int LOGN, int DEP>
+__global__ __launch_bounds__(kgeo<LOGN - DEP>::WG) void amqft_kL_rows(cx<R>* __restrict__ ws1,
+                                                                      const R* __restrict__ ktab) {
+    constexpr int LR = LOGN - DEP;  // rows = sides of a 2^LR-point transform
     using G = kgeo<LR>;
     constexpr bool SW = variant_traits<V>::switches;
-    constexpr int W3 = (1 << LOGN) / 16;  // = G::H
+    constexpr int W3 = (1 << LOGN) >> (DEP + 1);  // row width (= G::H)
     constexpr int N8r = G::N / 8;
     extern __shared__ __align__(16) unsigned char smem[];
     R* kt = reinterpret_cast<R*>(smem);
     R* kf = kt + G::Q;
     cx<R>* wall = reinterpret_cast<cx<R>*>(smem + (G::Q + G::KF_ALLOC) * sizeof(R));
     const int tid = threadIdx.x;
-    const int P = blockIdx.x;  // depth-3 path; rows (0, P) and (1, P)
+    const int P = blockIdx.x;  // path of the row pair
     cx<R>* sig = ws1 + (long long)blockIdx.y * (1 << LOGN);
-    // half hh (= context) holds the row of side hh ^ parity(P)
+    // half hh (= context) holds the row of side hh ^ parity(P) (depth 3) or
+    // the row of context hh (depth 6)
     cx<R>* row[2];
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) row[hh] = sig + ((hh ^ (SW ? par(P) : 0)) * 8 + P) * W3;
+    for (int hh = 0; hh < 2; ++hh)
+        row[hh] = DEP == 3 ? sig + ((hh ^ (SW ? par(P) : 0)) * 8 + P) * W3 : sig + (2 * P + hh) * W3;
     const int m0 = tid;
     cx<R> cd[2][8];
     if (m0 > 0) {
@@ -1110,7 +1119,7 @@ __global__ __launch_bounds__(kgeo<LOGN - 3>::WG) void amqft_kL_rows(cx<R>* __res
 #pragma unroll
             for (int k = 1; k < 8; ++k) cd[hh][k] = row[hh][(W3 / 8) * k];
     }
-    fill_constants<V, LR, R>(kt, kf, ktab, 3, false, tid);
+    fill_constants<V, LR, R>(kt, kf, ktab, DEP, false, tid);
     __syncthreads();
     if (m0 > 0) {
         const int pm = pad(m0);
@@ -1142,6 +1151,97 @@ __global__ __launch_bounds__(kgeo<LOGN - 3>::WG) void amqft_kL_rows(cx<R>* __res
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh)
         for (int pos = tid; pos < W3 - 8; pos += G::WG) row[hh][pos] = ldc(wall + hh * G::HS + pad(pos));
+}
+
+// N >= 2^18: levels 3..5 of every depth-3 row pair (the F1 levels of its
+// 2^(log2 N - 3)-point transform, constants at stride 8 in the table of N):
+// depth-6 rows -> ws2 by context; the slots that are multiples of W3 / 8 (the
+// row's blocks of 4, 2 and 1 points) are finished in place in ws1, at the
+// positions the row's block layout gives them.
+template <int V, typename R, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_rtop(cx<R>* __restrict__ ws1, cx<R>* __restrict__ ws2,
+                                                      const R* __restrict__ ktab) {
+    constexpr int LR = LOGN - 3;
+    constexpr bool SW = variant_traits<V>::switches;
+    constexpr int N = 1 << LOGN, W3 = N / 16, W6 = N / 128, N8r = (1 << LR) / 8;
+    const int m0 = blockIdx.x * 256 + threadIdx.x;  // < W6 (a multiple of 256)
+    const int P = blockIdx.y;                       // depth-3 path
+    cx<R>* sig1 = ws1 + (long long)blockIdx.z * N;
+    cx<R>* sig2 = ws2 + (long long)blockIdx.z * N;
+    cx<R>* row[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) row[hh] = sig1 + ((hh ^ (SW ? par(P) : 0)) * 8 + P) * W3;
+    cx<R> cd[2][8];
+    if (m0 > 0) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                cd[hh][2 * i] = row[hh][m0 + N8r * i];
+                cd[hh][2 * i + 1] = row[hh][N8r * (i + 1) - m0];
+            }
+    } else {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            cd[hh][0] = zero<R>();
+#pragma unroll
+            for (int k = 1; k < 8; ++k) cd[hh][k] = row[hh][(W3 / 8) * k];
+        }
+    }
+    // the slots that thread m0 = 0 overwrites below are read only by threads
+    // of this workgroup (m0 = 2 .. 8 of their orbits' last pair)
+    __syncthreads();
+    if (m0 > 0) {
+        f1_levels<V, LR, R, 3>(ktab, cd, m0, [&](auto sc, auto pc, cx<R> v) {
+            constexpr int hh = decltype(sc)::value, P8 = decltype(pc)::value;
+            constexpr int h2 = hh ^ (SW ? par(P8) : 0);
+            sig2[(2 * (8 * P + P8) + h2) * W6 + m0] = v;  // depth-6 row (8 P + P8) of context h2, slot m0
+        });
+    } else {
+        sfor<0, 2>([&](auto hc) {
+            constexpr int hh = decltype(hc)::value;
+            cx<R> b4[4] = {cd[hh][1], cd[hh][3], cd[hh][5], cd[hh][7]}, b2[2] = {cd[hh][2], cd[hh][6]};
+            leaf::ot<V, 4, hh, R>(b4, ktab, LOGN - 2);
+            leaf::ot<V, 2, hh, R>(b2, ktab, LOGN - 2);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) row[hh][W3 - 8 + i] = b4[i];
+            row[hh][W3 - 4] = b2[0];
+            row[hh][W3 - 3] = b2[1];
+            row[hh][W3 - 2] = cd[hh][4];
+        });
+    }
+}
+
+// N >= 2^18: levels 5..3 -- the eight depth-6 children of every depth-3 row
+// (in their block layout in ws2) back to that row's block layout in ws1
+// (blocks of at least 8 points; the smaller ones are already there)
+template <int V, typename R, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_rback(const cx<R>* __restrict__ ws2, cx<R>* __restrict__ ws1) {
+    constexpr bool SW = variant_traits<V>::switches;
+    constexpr int N = 1 << LOGN, W3 = N / 16, W6 = N / 128, LW6 = ilog2c(W6);
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= W6 - 1) return;
+    const int P = blockIdx.y >> 1, hh = blockIdx.y & 1;  // depth-3 row of path P and context hh
+    const cx<R>* sig2 = ws2 + (long long)blockIdx.z * N;
+    const int a = __clz(~(p << (32 - LW6)));  // block of position p in the child rows' block layout
+    const int j = p - (W6 - (W6 >> a));
+    const int sp = W6 >> (a + 1);
+    const int pm = p > 0 ? p - 1 : 0;
+    cx<R> ext[8][3];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const cx<R>* row = sig2 + (2 * (8 * P + q) + (hh ^ (SW ? par(q) : 0))) * W6;
+        const cx<R> lm = row[pm], lp = row[p + 1];
+        ext[q][0] = j >= 1 ? lm : zero<R>();
+        ext[q][1] = row[p];
+        ext[q][2] = j + 1 < sp ? lp : zero<R>();
+    }
+    cx<R>* out = ws1 + (long long)blockIdx.z * N + ((hh ^ (SW ? par(P) : 0)) * 8 + P) * W3 + (W3 - (W3 >> a)) + 8 * j;
+    cx<R> o[8];
+    if (hh == 0) bwd_run<V, 0, 3, R>(ext, o);
+    else bwd_run<V, 1, 3, R>(ext, o);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = o[e];
 }
 
 template <int V, typename R, int LOGN>
@@ -1194,10 +1294,11 @@ __global__ __launch_bounds__(256) void amqft_kL_chain(const cx<typename storage<
 template <int V, typename S, int LOGN>
 hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
     using R = typename storage<S>::R;
-    using G = kgeo<LOGN - 3>;
     constexpr int N = 1 << LOGN, W3 = N / 16;
+    constexpr int DEP = LOGN >= 18 ? 6 : 3;  // depth of the rows that fit one workgroup's LDS
+    using GR = kgeo<LOGN - DEP>;
     const int flags = (a.conj_in ? 1 : 0) | (a.conj_out ? 2 : 0);
-    const size_t lds = kA_lds_bytes<R, LOGN - 3>();
+    const size_t lds = kA_lds_bytes<R, LOGN - DEP>();
     cx<R>* ws1 = static_cast<cx<R>*>(a.ws1);
     cx<R>* ws2 = static_cast<cx<R>*>(a.ws2);
     cx<R>* wsc = static_cast<cx<R>*>(a.wsc);
@@ -1207,7 +1308,16 @@ hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
         const dim3 gw((W3 + 255) / 256, (unsigned)nb);
         hipLaunchKernelGGL((amqft_kL_top<V, S, LOGN>), gw, dim3(256), 0, st, static_cast<const S*>(a.in), ws1, wsc, kt,
                            s0, (long long)a.batch, flags, static_cast<const long long*>(a.offsets));
-        hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN>), dim3(8, (unsigned)nb), dim3(G::WG), lds, st, ws1, kt);
+        if constexpr (DEP == 3) {
+            hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN, 3>), dim3(8, (unsigned)nb), dim3(GR::WG), lds, st, ws1, kt);
+        } else {
+            constexpr int W6 = N / 128;
+            hipLaunchKernelGGL((amqft_kL_rtop<V, R, LOGN>), dim3(W6 / 256, 8, (unsigned)nb), dim3(256), 0, st, ws1, ws2,
+                               kt);
+            hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN, 6>), dim3(64, (unsigned)nb), dim3(GR::WG), lds, st, ws2, kt);
+            hipLaunchKernelGGL((amqft_kL_rback<V, R, LOGN>), dim3(W6 / 256, 16, (unsigned)nb), dim3(256), 0, st,
+                               static_cast<const cx<R>*>(ws2), ws1);
+        }
         hipLaunchKernelGGL((amqft_kL_back<V, R, LOGN>), gw, dim3(256), 0, st, static_cast<const cx<R>*>(ws1), ws2);
         hipLaunchKernelGGL((amqft_kL_chain<S, LOGN>), gw, dim3(256), 0, st, static_cast<const cx<R>*>(ws2),
                            static_cast<const cx<R>*>(wsc), static_cast<S*>(a.out), s0, (long long)a.batch, flags,
@@ -1218,19 +1328,28 @@ hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
 
 template <int V, typename S>
 hipError_t launch_kL_s(const kl_launch& a, hipStream_t st) {
-    switch (a.logn) {
-    case 15: return launch_kL_n<V, S, 15>(a, st);
-    case 16: return launch_kL_n<V, S, 16>(a, st);
-    default: return launch_kL_n<V, S, 17>(a, st);
+    if constexpr (std::is_same<S, double2>::value) {
+        if (a.logn == 15) return launch_kL_n<V, S, 15>(a, st);
+        return launch_kL_n<V, S, 16>(a, st);
+    } else {
+        switch (a.logn) {
+        case 15: return launch_kL_n<V, S, 15>(a, st);
+        case 16: return launch_kL_n<V, S, 16>(a, st);
+        case 17: return launch_kL_n<V, S, 17>(a, st);
+        case 18: return launch_kL_n<V, S, 18>(a, st);
+        case 19: return launch_kL_n<V, S, 19>(a, st);
+        default: return launch_kL_n<V, S, 20>(a, st);
+        }
     }
 }
 
-template <int V, typename R, int LOGN>
+template <int V, typename R, int LOGN, int LMAX>
 hipError_t prime_kL_n() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kL_rows<V, R, LOGN>),
+    constexpr int DEP = LOGN >= 18 ? 6 : 3;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kL_rows<V, R, LOGN, DEP>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if constexpr (LOGN < 17) {
-        if (e == hipSuccess) e = prime_kL_n<V, R, LOGN + 1>();
+    if constexpr (LOGN < LMAX) {
+        if (e == hipSuccess) e = prime_kL_n<V, R, LOGN + 1, LMAX>();
     }
     return e;
 }
@@ -1295,14 +1414,15 @@ hipError_t launch_kA_loss(const loss_launch& a, hipStream_t st) {
 bool kL_supported(int variant, int logn, int dtype) {
     if (variant != 4 && variant != 8) return false;
     if (dtype == 0) return logn >= 15 && logn <= 16;
-    return logn >= 15 && logn <= 17;  // FP32 arithmetic: FP32, FP16 and BF16 storage
+    return logn >= 15 && logn <= 20;  // FP32 arithmetic: FP32, FP16 and BF16 storage
 }
 
 size_t kL_ws_bytes_per_signal(int logn, int dtype) { return ((size_t)1 << logn) * (dtype == 0 ? 16 : 8); }
 
 hipError_t prime_kL(int variant, int dtype) {
-    if (variant == 4) return dtype == 0 ? prime_kL_n<4, double, 15>() : prime_kL_n<4, float, 15>();
-    if (variant == 8) return dtype == 0 ? prime_kL_n<8, double, 15>() : prime_kL_n<8, float, 15>();  // R = float for 1..3
+    // the rows kernels depend on the arithmetic type only (float for dtypes 1..3)
+    if (variant == 4) return dtype == 0 ? prime_kL_n<4, double, 15, 16>() : prime_kL_n<4, float, 15, 20>();
+    if (variant == 8) return dtype == 0 ? prime_kL_n<8, double, 15, 16>() : prime_kL_n<8, float, 15, 20>();
     return hipSuccess;
 }
 

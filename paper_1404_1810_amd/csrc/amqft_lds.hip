@@ -417,6 +417,35 @@ hipError_t prime_lds(int variant, int dtype) {
     }
 }
 
+// constants of family fam for length 2^logn, entries p < N/4, computed on the
+// device in FP64 (cospi / sinpi) and rounded once to R (the same values the
+// kernels generate per workgroup under AMQFT_FLAG_ONTHEFLY_CONSTANTS)
+template <typename R>
+__global__ __launch_bounds__(256) void amqft_fill_table_kernel(R* __restrict__ kt, int fam, int logn) {
+    const long long q = 1ll << (logn - 2);
+    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= q) return;
+    const double x = (double)p * 2.0 / (double)(1ll << logn);
+    double v;
+    if (fam == 0) v = 2.0 * cospi(x);
+    else if (fam == 1) v = 1.0 / (2.0 * cospi(x));
+    else if (fam == 2) v = 2.0 * sinpi(x);
+    else v = 1.0 / (2.0 * sinpi(x));
+    kt[p] = p == 0 ? R(0) : R(v);
+}
+
+hipError_t fill_table_device(void* ktab, int variant, int dtype, int logn, hipStream_t st) {
+    const long long q = 1ll << (logn - 2);
+    const dim3 grid((unsigned)((q + 255) / 256));
+    if (dtype == 0)
+        hipLaunchKernelGGL((amqft_fill_table_kernel<double>), grid, dim3(256), 0, st, static_cast<double*>(ktab),
+                           const_family(variant), logn);
+    else
+        hipLaunchKernelGGL((amqft_fill_table_kernel<float>), grid, dim3(256), 0, st, static_cast<float*>(ktab),
+                           const_family(variant), logn);
+    return hipGetLastError();
+}
+
 void describe_lds(const lds_launch& a, char* buf, size_t len) {
     static const char* st[4] = {"double2", "float2", "__half2", "bf16x2"};
     const char* sname = st[a.dtype & 3];

@@ -192,3 +192,34 @@ def test_large_path(variant, monkeypatch):
                 assert ea <= b, (dtype, n, "adjoint", ea, b)
             plan.close()
         assert x.dtype == tdt
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", [4, 8])
+def test_large_path_deep(variant):
+    """N = 2^18 and 2^20 (FP32) on the six-kernel path: depth-3 rows split once
+    more into depth-6 rows; table and device-generated constants, adjoint."""
+    api = _api()
+    from paper_1404_1810_amd import _lib
+    for n, batch in ((1 << 18, 2), (1 << 20, 1)):
+        _say("deep large path c64 variant", variant, "n", n, "batch", batch)
+        x_np = inputs.complex_normal(6000 + n, batch, n).astype(np.complex64)
+        ref = truth(x_np, 4)
+        b = bound(variant, False, x_np, ref)
+        x = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
+        for flags in (0, _lib.FLAG_ONTHEFLY_CONSTANTS):
+            plan = api.Plan(n, batch, variant, _lib.C64, flags)
+            assert "rtop" in plan.describe(), plan.describe()
+            y = plan.exec(x)
+            torch.cuda.synchronize()
+            e = rel(y.cpu().numpy(), ref)
+            _say("  flags", flags, "rel err", e, "bound", b)
+            # (variant 8 overflows FP32 at 2^20 in the oracle's FP32 build too:
+            # no finite bound, the result is reported only)
+            assert not np.isfinite(b) or e <= b, (n, flags, e, b)
+            if flags == 0 and n == 1 << 18 and np.isfinite(b):
+                g = plan.exec(x, adjoint=True)
+                torch.cuda.synchronize()
+                ea = rel(g.cpu().numpy(), np.conj(truth(np.conj(x_np), 4)))
+                assert ea <= b, (n, "adjoint", ea, b)
+            plan.close()
