@@ -60,6 +60,42 @@ __device__ __forceinline__ void sfor(F&& f) {
 template <typename R>
 __device__ __forceinline__ cx<R> zero() { return cx<R>{R(0), R(0)}; }
 
+// One signal of S values seen through a buffer resource: a base address in
+// scalar registers, element offsets split into a lane part and a scalar part,
+// so that addressing costs no vector instructions (the base must be the same
+// in every lane of the wave).
+template <typename S>
+struct sigbuf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ sigbuf(const S* p, int n)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(p), (short)0, n * (int)sizeof(S), 0x00020000)) {}
+    __device__ __forceinline__ S ld(int lane_elems, int scalar_elems) const {
+        const int vo = lane_elems * (int)sizeof(S), so = scalar_elems * (int)sizeof(S);
+        if constexpr (sizeof(S) == 16) return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+        else if constexpr (sizeof(S) == 8) return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+        else return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    __device__ __forceinline__ void st(int lane_elems, int scalar_elems, S v) const {
+        const int vo = lane_elems * (int)sizeof(S), so = scalar_elems * (int)sizeof(S);
+        if constexpr (sizeof(S) == 16) {
+            using U = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, vo, so, 0);
+        } else if constexpr (sizeof(S) == 8) {
+            using U = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, vo, so, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+        }
+    }
+};
+
+// a value known to be the same in every lane, moved to scalar registers
+__device__ __forceinline__ long long uniform64(long long v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 template <int SG, typename R>
 __device__ __forceinline__ void bfly(cx<R> x, cx<R> y, R k, cx<R>& lo, cx<R>& hi) {
     if constexpr (SG == 0) {
@@ -184,13 +220,28 @@ constexpr size_t kA_lds_bytes() {
 // ---------------------------------------------------------------------------
 // F1
 // ---------------------------------------------------------------------------
-template <int LOGN, typename S, typename R>
-__device__ __forceinline__ void f1_load(const S* x, int m0, bool live, cx<R> (&raw)[16]) {
+// The 16 points of thread m0's orbit.  Workgroup slots past the end of the
+// batch load signal 0 instead (valid memory; their results are never stored).
+// WAVE_UNIFORM: x is the same in every lane of the wave (buffer addressing).
+template <int LOGN, typename S, typename R, bool WAVE_UNIFORM = false>
+__device__ __forceinline__ void f1_load(const S* x, int m0, cx<R> (&raw)[16]) {
     constexpr int N8 = (1 << LOGN) / 8, N16 = (1 << LOGN) / 16;
-    if (!live) {
+    if constexpr (WAVE_UNIFORM) {
+        const sigbuf<S> b(x, 1 << LOGN);
+        auto w = [](S v) { return storage<S>::ld(&v); };
+        if (m0 > 0) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) raw[j] = zero<R>();
-    } else if (m0 > 0) {
+            for (int j = 0; j < 8; ++j) {
+                raw[j] = w(b.ld(m0, N8 * j));
+                raw[8 + j] = w(b.ld(N8 - m0, N8 * j));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) raw[k] = w(b.ld(0, N16 * k));
+        }
+        return;
+    }
+    if (m0 > 0) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             raw[j] = storage<S>::ld(x + m0 + N8 * j);
@@ -777,10 +828,29 @@ __device__ __forceinline__ void c0_compute(const cx<R>* w, const cx<R>* chn, int
 }
 
 // store the 16 values of a thread at its orbit indices (the F1 load pattern)
-template <int LOGN, typename S, typename R>
+template <int LOGN, typename S, typename R, bool WAVE_UNIFORM = false>
 __device__ __forceinline__ void c0_store(S* y, int k0, const cx<R> (&res)[16], bool conj_out) {
     constexpr int N8 = (1 << LOGN) / 8, N16 = (1 << LOGN) / 16;
     auto c = [&](cx<R> v) { return conj_out ? cconj(v) : v; };
+    if constexpr (WAVE_UNIFORM) {
+        const sigbuf<S> b(y, 1 << LOGN);
+        auto n = [](cx<R> v) {
+            S o;
+            storage<S>::st(&o, v);
+            return o;
+        };
+        if (k0 > 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                b.st(k0, N8 * j, n(c(res[j])));
+                b.st(N8 - k0, N8 * j, n(c(res[8 + j])));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) b.st(0, N16 * i, n(c(res[i])));
+        }
+        return;
+    }
     if (k0 > 0) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -843,10 +913,14 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_kernel(const S* __res
     const int fs = tid / G::T, m0 = tid - fs * G::T;  // signal of this thread in F1 / B0 / C0, orbit index
     const long long gs = (long long)blockIdx.x * G::SPW + fs;
     const bool live = gs < batch;
-    const long long base = !live ? 0 : offsets ? offsets[gs] : gs * (long long)G::N;
+    long long base = !live ? 0 : offsets ? offsets[gs] : gs * (long long)G::N;
+    // at least one wave per signal: the signal's offset is the same in every
+    // lane, so loads and stores address it from scalar registers
+    constexpr bool WU = G::T >= 64;
+    if constexpr (WU) base = uniform64(base);
 
     cx<R> raw[16];
-    f1_load<LOGN, S, R>(in + base, m0, live, raw);
+    f1_load<LOGN, S, R, WU>(in + base, m0, raw);
     fill_constants<V, LOGN, R>(kt, kf, ktab, kshift, onthefly, tid);
     __syncthreads();
 
@@ -862,7 +936,7 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_kernel(const S* __res
     if (live) {
         cx<R> res[16];
         c0_compute<LOGN, R, lds_layout<LOGN>>(w, w, m0, res);
-        c0_store<LOGN, S, R>(out + base, m0, res, conj_out);
+        c0_store<LOGN, S, R, WU>(out + base, m0, res, conj_out);
     }
 }
 
@@ -895,11 +969,13 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_loss_kernel(const S* 
     const int fs = tid / G::T, m0 = tid - fs * G::T;
     const long long gs = (long long)blockIdx.x * G::SPW + fs;
     const bool live = gs < batch;
-    const long long base = live ? gs * (long long)G::N : 0;
+    constexpr bool WU = G::T >= 64;  // one signal per wave or more: uniform offsets
+    long long base = live ? gs * (long long)G::N : 0;
+    if constexpr (WU) base = uniform64(base);
     cx<R>* w = wall + fs * G::SL;
 
     cx<R> raw[16];
-    f1_load<LOGN, S, R>(xin + base, m0, live, raw);
+    f1_load<LOGN, S, R, WU>(xin + base, m0, raw);
     fill_constants<V, LOGN, R>(kt, kf, ktab, kshift, onthefly, tid);
     __syncthreads();
 
@@ -916,7 +992,7 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_loss_kernel(const S* 
 
     // weighting: g = 2 |W|^2 y at the thread's 16 indices; loss partial
     cx<R> wt[16];
-    f1_load<LOGN, S, R>(win + base, m0, live, wt);
+    f1_load<LOGN, S, R, WU>(win + base, m0, wt);
     R part = R(0);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -952,7 +1028,7 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_loss_kernel(const S* 
     b0_pass<V, LOGN, R>(wall, tid);
     if (live) {
         c0_compute<LOGN, R, lds_layout<LOGN>>(w, w, m0, y);
-        c0_store<LOGN, S, R>(grad + base, m0, y, true);
+        c0_store<LOGN, S, R, WU>(grad + base, m0, y, true);
     }
 }
 
@@ -1061,9 +1137,9 @@ __global__ __launch_bounds__(256) void amqft_kL_top(const S* __restrict__ in, cx
     const long long sl = blockIdx.y, gs = sig0 + sl;
     if (gs >= batch || m0 >= W3) return;
     const bool conj_in = flags & 1;
-    const long long base = offsets ? offsets[gs] : gs * (long long)N;
+    const long long base = uniform64(offsets ? offsets[gs] : gs * (long long)N);
     cx<R> raw[16];
-    f1_load<LOGN, S, R>(in + base, m0, true, raw);
+    f1_load<LOGN, S, R, true>(in + base, m0, raw);
     cx<R>* rows = ws1 + sl * N;
     if (m0 > 0) {
         cx<R> cd[2][8];
@@ -1285,10 +1361,10 @@ __global__ __launch_bounds__(256) void amqft_kL_chain(const cx<typename storage<
     const int k0 = blockIdx.x * 256 + threadIdx.x;
     const long long sl = blockIdx.y, gs = sig0 + sl;
     if (gs >= batch || k0 >= W3) return;
-    const long long base = offsets ? offsets[gs] : gs * (long long)N;
+    const long long base = uniform64(offsets ? offsets[gs] : gs * (long long)N);
     cx<R> res[16];
     c0_compute<LOGN, R, global_layout<LOGN>>(ws2 + sl * N, wsc + sl * 16, k0, res);
-    c0_store<LOGN, S, R>(out + base, k0, res, (flags & 2) != 0);
+    c0_store<LOGN, S, R, true>(out + base, k0, res, (flags & 2) != 0);
 }
 
 template <int V, typename S, int LOGN>
