@@ -68,12 +68,14 @@ hipError_t launch_fast(const lds_launch& a, hipStream_t stream);
 hipError_t prime_fast(int variant, int dtype);
 void fast_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
 
-// Skeleton-A kernels for N = 2^8 .. 2^14 (variants 4 and 8; FP64 up to 2^13)
+// Skeleton-A kernels for N = 2^8 .. 2^14 (variants 1, 4, 5, 8; FP64 up to 2^13)
 // with the dataflow fixed at compile time (amqft_kA.hip).
 bool kA_supported(int variant, int logn, int dtype);
 hipError_t launch_kA(const lds_launch& a, hipStream_t stream);
 hipError_t prime_kA(int variant, int dtype);
 void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
+// dynamic LDS bytes of the compile-time kernel for one variant
+size_t kA_lds(int variant, int logn, int dtype);
 // N = 2^15 .. 2^17 (FP64 to 2^16), variants 4 and 8: four kernels over a
 // global workspace (top levels, rows through the kA kernels, back levels,
 // chain); signals run in chunks of `chunk`.

@@ -670,6 +670,363 @@ __device__ __forceinline__ void b0_pass(cx<R>* wall, int tid) {
 }
 
 // ---------------------------------------------------------------------------
+// M1 / M5: the backward M^F is a recurrence along each hi child, first term
+// halved (Tables 5-6): M1 G(i) = H(i) - G(i -+ 1), M5 G(i) = H(i) + G(i -+ 1),
+// ascending for (M1, DCT parent) and (M5, DST parent), descending otherwise.
+// With G(i) = (-1)^i U(i) for M1 it is an inclusive prefix (suffix) sum U of
+// u(k) = (-1)^k h'(k), h' the child with its first element halved.  Each lane
+// holds n consecutive entries of the child; the sum runs in the lane, then
+// across the lanes of the child as a segmented scan on lane shuffles.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ cx<R> shfl_up_c(cx<R> v, int d) {
+    return cx<R>{__shfl_up(v.re, d), __shfl_up(v.im, d)};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> shfl_dn_c(cx<R> v, int d) {
+    return cx<R>{__shfl_down(v.re, d), __shfl_down(v.im, d)};
+}
+
+template <int V, int SG>
+struct rec_dir {
+    static constexpr bool asc = (V == 1) ? (SG == 0) : (SG != 0);
+    static constexpr bool alt = variant_traits<V>::sign < 0;
+};
+
+// exclusive sum of t over the lanes before (ASC) or after this one in its
+// segment of nl lanes (pos = index in the segment, segments of at most MAXL
+// consecutive lanes inside one wave); every lane of the wave must call it
+template <bool ASC, int MAXL, typename R>
+__device__ __forceinline__ cx<R> seg_excl(cx<R> t, int pos, int nl) {
+    const cx<R> z = zero<R>();
+    cx<R> w;
+    if constexpr (ASC) {
+        const cx<R> u1 = shfl_up_c(t, 1);
+        w = pos >= 1 ? u1 : z;
+    } else {
+        const cx<R> d1 = shfl_dn_c(t, 1);
+        w = pos + 1 < nl ? d1 : z;
+    }
+#pragma unroll
+    for (int d = 1; d < MAXL; d <<= 1) {
+        if constexpr (ASC) {
+            const cx<R> u = shfl_up_c(w, d);
+            if (pos >= d) w = w + u;
+        } else {
+            const cx<R> u = shfl_dn_c(w, d);
+            if (pos + d < nl) w = w + u;
+        }
+    }
+    return w;
+}
+
+// One entry per lane (n = 1): the sums are formed over the index pairs
+// {2m, 2m+1} first and then across pairs.  (Grouping the alternating terms
+// the other way, {2m-1, 2m}, loses up to two decimal digits on these
+// spectra.)  carry = exclusive sum over the pairs before (after) this lane's
+// pair; own = the partial sum inside the pair up to this lane.
+template <bool ASC, int MAXL, typename R>
+__device__ __forceinline__ void pair_excl(cx<R> u, int pos, int nl, cx<R>& carry, cx<R>& own) {
+    const cx<R> z = zero<R>();
+    const cx<R> up = shfl_up_c(u, 1), dn = shfl_dn_c(u, 1);
+    const bool odd = pos & 1, paired = nl > 1;
+    const cx<R> ps = !paired ? u : odd ? up + u : u + dn;  // u(2m) + u(2m+1)
+    own = paired && (ASC ? odd : !odd) ? ps : u;
+    const int pm = pos >> 1, np = paired ? nl >> 1 : 1;
+    cx<R> w;
+    if constexpr (ASC) {
+        const cx<R> a = shfl_up_c(ps, 2);
+        w = pm >= 1 ? a : z;
+    } else {
+        const cx<R> a = shfl_dn_c(ps, 2);
+        w = pm + 1 < np ? a : z;
+    }
+#pragma unroll
+    for (int d = 1; 2 * d < MAXL; d <<= 1) {
+        if constexpr (ASC) {
+            const cx<R> a = shfl_up_c(w, 2 * d);
+            if (pm >= d) w = w + a;
+        } else {
+            const cx<R> a = shfl_dn_c(w, 2 * d);
+            if (pm + d < np) w = w + a;
+        }
+    }
+    carry = w;
+}
+
+// first half of one recurrence level: local sums loc[] of the lane's n hi
+// entries in scan order and their total
+template <int V, int SG, int n, typename R>
+__device__ __forceinline__ cx<R> rec_local(const cx<R>* Hh, int pos, int nl, cx<R> (&loc)[n]) {
+    using RD = rec_dir<V, SG>;
+    const int len = nl * n;
+    cx<R> u[n];
+#pragma unroll
+    for (int e = 0; e < n; ++e) {
+        const int i = pos * n + e;
+        cx<R> v = Hh[e];
+        if (len > 1 && (RD::asc ? i == 0 : i == len - 1)) v = v * R(0.5);
+        if (RD::alt && (i & 1)) v = cx<R>{-v.re, -v.im};
+        u[e] = v;
+    }
+    if constexpr (RD::asc) {
+        loc[0] = u[0];
+#pragma unroll
+        for (int e = 1; e < n; ++e) loc[e] = loc[e - 1] + u[e];
+        return loc[n - 1];
+    } else {
+        loc[n - 1] = u[n - 1];
+#pragma unroll
+        for (int e = n - 2; e >= 0; --e) loc[e] = loc[e + 1] + u[e];
+        return loc[0];
+    }
+}
+
+// second half: add the carry, undo the sign pattern, interleave with the lo
+// child into the parent run P[0 .. 2n)
+template <int V, int SG, int n, typename R>
+__device__ __forceinline__ void rec_finish(const cx<R>* L, const cx<R>* Hh, const cx<R> (&loc)[n], cx<R> carry,
+                                           cx<R> own, int pos, int nl, cx<R>* P) {
+    using RD = rec_dir<V, SG>;
+    const int len = nl * n;
+#pragma unroll
+    for (int e = 0; e < n; ++e) {
+        const int i = pos * n + e;
+        cx<R> g = (n == 1 ? own : loc[e]) + carry;
+        if (RD::alt && (i & 1)) g = cx<R>{-g.re, -g.im};
+        if (len == 1) g = Hh[e];  // L = 8 base: no M step
+        if constexpr (SG == 0) {
+            P[2 * e] = L[e];
+            P[2 * e + 1] = g;
+        } else {
+            P[2 * e] = g;
+            P[2 * e + 1] = L[e];
+        }
+    }
+}
+
+// r backward levels below a parent of context SGB for one lane (its segment
+// position pos of nl lanes): cur[q][0] = child q's entry, cur[0][0 .. 2^r) out
+template <int V, int SGB, int r, int t, int MAXL, typename R>
+__device__ __forceinline__ void rec_levels(cx<R> (&cur)[1 << r][1 << r], int pos, int nl) {
+    if constexpr (t < r) {
+        constexpr bool SW = variant_traits<V>::switches;
+        constexpr int nrow = 1 << (r - t - 1), n = 1 << t;
+        sfor<0, nrow>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int sg = SGB ^ (SW ? par(q) : 0);
+            constexpr bool ASC = rec_dir<V, sg>::asc;
+            cx<R> loc[n];
+            const cx<R> tot = rec_local<V, sg, n, R>(cur[2 * q + 1], pos, nl, loc);
+            cx<R> carry, own = tot;
+            if constexpr (n == 1) pair_excl<ASC, MAXL, R>(loc[0], pos, nl, carry, own);
+            else carry = seg_excl<ASC, MAXL, R>(tot, pos, nl);
+            cx<R> tmp[2 * n];
+            rec_finish<V, sg, n, R>(cur[2 * q], cur[2 * q + 1], loc, carry, own, pos, nl, tmp);
+#pragma unroll
+            for (int e = 0; e < 2 * n; ++e) cur[q][e] = tmp[e];
+        });
+        rec_levels<V, SGB, r, t + 1, MAXL, R>(cur, pos, nl);
+    }
+}
+
+// B_K for M1 / M5: lane wm = 0 .. GL - 2 of a row holds child index j of the
+// block of its position (so that every child's lanes form an aligned group
+// inside one wave); the last lane of each row idles
+template <int V, int LOGN, int K, typename R>
+__device__ __forceinline__ void bpass_rec(cx<R>* wall, int tid) {
+    using G = kgeo<LOGN>;
+    using M = mpass<LOGN, K>;
+    constexpr bool SW = variant_traits<V>::switches;
+    constexpr int NV = M::NV, IT = M::IT, LG = ilog2c(M::GL), MAXL = M::GL / 2;
+    cx<R> cur[IT][NV][NV];
+    task tk[IT];
+    int jj[IT], spp[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        tk[it] = mtask<LOGN, K>(it, tid);
+        const task t = tk[it];
+        const int wm = t.m;
+        const int a = __clz(~(wm << (32 - LG)));  // leading ones of wm in LG bits (LG: idle lane)
+        const bool act = wm < M::GL - 1;
+        const int j = act ? wm - (M::GL - (M::GL >> a)) : 0;
+        const int sp = act ? M::GL >> (a + 1) : 0;
+        jj[it] = j;
+        spp[it] = sp;
+        int off[3] = {0, 0, 0};
+        if (act) child_offsets<LOGN, K>(a, j, sp, off);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const int hq = t.h ^ (SW ? par(q) : 0);
+            const cx<R>* row = wall + t.s * G::SL + hq * G::HS + (t.P * NV + q) * M::GP;
+            cur[it][q][0] = act ? ldc(row + off[1]) : zero<R>();
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const task t = tk[it];
+        // t.h is the same in every lane of a wave (a half holds a multiple of 64 tasks)
+        if (t.h == 0) rec_levels<V, 0, M::r, 0, MAXL, R>(cur[it], jj[it], spp[it]);
+        else rec_levels<V, 1, M::r, 0, MAXL, R>(cur[it], jj[it], spp[it]);
+        if (t.m < M::GL - 1) {
+            cx<R>* dst = wall + t.s * G::SL + t.h * G::HS + t.P * M::WP + pad(NV * (t.m + 1));  // main array at 2^r m
+#pragma unroll
+            for (int e = 0; e < NV; ++e) stc(dst + e, cur[it][0][e]);
+        }
+    }
+    __syncthreads();
+}
+
+// LDS scratch of the M1 / M5 backward passes: per signal, per wave, two sides
+// times four rows of partial sums (segments longer than one wave)
+template <int LOGN>
+constexpr int kA_rec_scratch() {
+    using G = kgeo<LOGN>;
+    return G::W3 / 2 > 64 ? G::SPW * (G::T / 64) * 8 : 0;
+}
+
+// LDS of amqft_kA_kernel for variant V (M1 / M5 add the scratch above)
+template <int V, typename R, int LOGN>
+constexpr size_t kA_lds_bytes_v() {
+    return kA_lds_bytes<R, LOGN>() + (variant_traits<V>::recurrence ? (size_t)kA_rec_scratch<LOGN>() * sizeof(cx<R>) : 0);
+}
+
+// B0 for M1 / M5: levels 2..0 of both sides.  Lanes are remapped so that the
+// main-array blocks of the depth-3 rows start at lane 0 (aligned segments,
+// those longer than a wave aligned to waves) and the small blocks of the
+// first middle pass (or of P3) sit in the last lanes.
+template <int V, int LOGN, typename R>
+__device__ __forceinline__ void b0_pass_rec(cx<R>* wall, cx<R>* scr, int tid) {
+    using G = kgeo<LOGN>;
+    constexpr bool SW = variant_traits<V>::switches;
+    constexpr int LW3 = ilog2c(G::W3);
+    constexpr bool MULTI = G::W3 / 2 > 64;  // segments spanning several waves
+    constexpr int MAXL = G::W3 / 2 < 64 ? G::W3 / 2 : 64;
+    const int s = tid / G::T, L = tid - s * G::T;
+    int a = 0, j = 0, sp = 0, p = 0;
+    int off[3] = {0, 0, 0};
+    if constexpr (G::NP == 0) {
+        p = L;  // depth 3 = P3 rows: [8 | 4 | 2 | 1] at slots 1..15
+        if (p > 0) {
+            const int e = p - 1;
+            const int b = e < 8 ? 0 : e < 12 ? 1 : e < 14 ? 2 : 3;
+            sp = 8 >> b;
+            j = e - (16 - 2 * sp);
+            a = b;
+            off[1] = pad(p);
+        }
+    } else {
+        using M0 = mpass<LOGN, 0>;
+        constexpr int r0 = M0::r, G0 = M0::GL, NS = 1 << r0;
+        if (L < G::W3 - NS) {
+            const int pp = L;
+            p = pp + NS;
+            a = __clz(~(pp << (32 - LW3)));
+            j = pp - (G::W3 - (G::W3 >> a));
+            sp = G::W3 >> (a + 1);
+            off[1] = pad(p);
+        } else {
+            p = L - (G::W3 - NS);
+            if (p > 0) {
+                const int e = p - 1;  // finished by pass 0: pad slots
+                const int b = __clz(~(e << (32 - r0)));
+                sp = (1 << (r0 - 1)) >> b;
+                j = e - ((1 << r0) - 2 * sp);
+                a = LW3 - r0 + b;
+                off[1] = 17 * ((e + 1) * (G0 / 16)) + 16;
+            }
+        }
+    }
+    const bool act = p > 0;
+    cx<R> cur[2][8][8];
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int hq = side ^ (SW ? par(q) : 0);
+            const cx<R>* row = wall + s * G::SL + hq * G::HS + q * G::W3P;
+            cur[side][q][0] = act ? ldc(row + off[1]) : zero<R>();
+        }
+    __syncthreads();
+    const int wl = L & 63;                       // lane in the wave
+    const int wv = L >> 6;                       // wave of the signal
+    const int seg0 = L - j;                      // first lane of the segment
+    const bool multi = MULTI && sp > 64;
+    const int pw = multi ? wl : j, nw = multi ? 64 : sp;  // position / length inside this wave
+    cx<R>* sc = scr + s * ((G::T / 64) * 8);
+    sfor<0, 3>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        constexpr int n = 1 << t, NR = 1 << (2 - t);
+        cx<R> loc[2][NR][n], own[2][NR], car[2][NR];
+        sfor<0, 2>([&](auto sc2) {
+            constexpr int side = decltype(sc2)::value;
+            sfor<0, NR>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int sg = side ^ (SW ? par(q) : 0);
+                constexpr bool ASC = rec_dir<V, sg>::asc;
+                own[side][q] = rec_local<V, sg, n, R>(cur[side][2 * q + 1], j, sp, loc[side][q]);
+                if constexpr (n == 1) pair_excl<ASC, MAXL, R>(loc[side][q][0], pw, nw, car[side][q], own[side][q]);
+                else car[side][q] = seg_excl<ASC, MAXL, R>(own[side][q], pw, nw);
+            });
+        });
+        if constexpr (MULTI) {
+            // wave totals of the long segments, then the carry of the waves before (after)
+            sfor<0, 2>([&](auto sc2) {
+                constexpr int side = decltype(sc2)::value;
+                sfor<0, NR>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    constexpr int sg = side ^ (SW ? par(q) : 0);
+                    constexpr bool ASC = rec_dir<V, sg>::asc;
+                    if (multi && wl == (ASC ? 63 : 0)) stc(sc + wv * 8 + side * 4 + q, own[side][q] + car[side][q]);
+                });
+            });
+            __syncthreads();
+            if (multi) {
+                const int w0 = seg0 >> 6, w1 = (seg0 + sp - 1) >> 6;
+                sfor<0, 2>([&](auto sc2) {
+                    constexpr int side = decltype(sc2)::value;
+                    sfor<0, NR>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        constexpr int sg = side ^ (SW ? par(q) : 0);
+                        constexpr bool ASC = rec_dir<V, sg>::asc;
+                        cx<R> c = zero<R>();
+                        if (ASC) {
+                            for (int w = w0; w < wv; ++w) c = c + ldc(sc + w * 8 + side * 4 + q);
+                        } else {
+                            for (int w = wv + 1; w <= w1; ++w) c = c + ldc(sc + w * 8 + side * 4 + q);
+                        }
+                        car[side][q] = car[side][q] + c;
+                    });
+                });
+            }
+            __syncthreads();
+        }
+        sfor<0, 2>([&](auto sc2) {
+            constexpr int side = decltype(sc2)::value;
+            sfor<0, NR>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int sg = side ^ (SW ? par(q) : 0);
+                cx<R> tmp[2 * n];
+                rec_finish<V, sg, n, R>(cur[side][2 * q], cur[side][2 * q + 1], loc[side][q], car[side][q],
+                                        own[side][q], j, sp, tmp);
+#pragma unroll
+                for (int e = 0; e < 2 * n; ++e) cur[side][q][e] = tmp[e];
+            });
+        });
+    });
+    if (act) {
+        const int ob = pad(G::H - (G::H >> a) + 8 * j);  // block a at H - H / 2^a at depth 0
+        cx<R>* ws = wall + s * G::SL;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) stc(ws + ob + e, cur[0][0][e]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) stc(ws + G::HS + ob + e, cur[1][0][e]);
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // C0: chain and D_c.  res[] comes out in the order of the thread's F1 orbit:
 // res[j] = X(k0 + (N/8) j), res[8 + j] = X((N/8)(j+1) - k0), j = 0..7, or for
 // k0 = 0, res[i] = X((N/16) i): the same 16 indices the thread loads in F1.
@@ -875,7 +1232,10 @@ __device__ __forceinline__ void fill_constants(R* kt, R* kf, const R* __restrict
         if (!onthefly) return ktab[(long)p << kshift];
         const double a = (double)p * 2.0 / (double)G::N;
         constexpr int fam = const_family(V);
-        const double d = fam == 1 ? 1.0 / (2.0 * cospi(a)) : 1.0 / (2.0 * sinpi(a));
+        const double d = fam == 0 ? 2.0 * cospi(a)
+                         : fam == 1 ? 1.0 / (2.0 * cospi(a))
+                         : fam == 2 ? 2.0 * sinpi(a)
+                                    : 1.0 / (2.0 * sinpi(a));
         return p == 0 ? R(0) : R(d);
     };
     for (int p = tid; p < G::Q; p += G::WG) kt[p] = kval(p);
@@ -931,8 +1291,13 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kA_kernel(const S* __res
 
     sfor<0, G::NP>([&](auto kc) { orbit_pass<V, LOGN, decltype(kc)::value, R>(wall, kt, kf, tid); });
     p3_pass<V, LOGN, R>(wall, kt, tid);
-    sfor<0, G::NP>([&](auto kc) { bpass<V, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, tid); });
-    b0_pass<V, LOGN, R>(wall, tid);
+    if constexpr (variant_traits<V>::recurrence) {
+        sfor<0, G::NP>([&](auto kc) { bpass_rec<V, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, tid); });
+        b0_pass_rec<V, LOGN, R>(wall, wall + G::SPW * G::SL, tid);
+    } else {
+        sfor<0, G::NP>([&](auto kc) { bpass<V, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, tid); });
+        b0_pass<V, LOGN, R>(wall, tid);
+    }
     if (live) {
         cx<R> res[16];
         c0_compute<LOGN, R, lds_layout<LOGN>>(w, w, m0, res);
@@ -1074,7 +1439,7 @@ hipError_t launch_kA_n(const lds_launch& a, hipStream_t st) {
     using G = kgeo<LOGN>;
     const int flags = (a.conj_in ? 1 : 0) | (a.conj_out ? 2 : 0) | (a.onthefly ? 4 : 0);
     const long long grid = (a.batch + G::SPW - 1) / G::SPW;
-    const size_t lds = kA_lds_bytes<R, LOGN>();
+    const size_t lds = kA_lds_bytes_v<V, R, LOGN>();
     hipLaunchKernelGGL((amqft_kA_kernel<V, S, LOGN>), dim3((unsigned)grid), dim3(G::WG), lds, st,
                        static_cast<const S*>(a.in), static_cast<S*>(a.out), static_cast<const R*>(a.ktab),
                        (long long)a.batch, a.ktab_log2n - LOGN, flags, static_cast<const long long*>(a.offsets));
@@ -1433,9 +1798,26 @@ hipError_t prime_kL_n() {
 }  // namespace
 
 bool kA_supported(int variant, int logn, int dtype) {
-    if (variant != 4 && variant != 8) return false;
+    if (variant != 1 && variant != 4 && variant != 5 && variant != 8) return false;
     if (dtype == 0) return logn >= 8 && logn <= 13;
     return logn >= 8 && logn <= 14;  // FP32 arithmetic: FP32, FP16 and BF16 storage
+}
+
+template <int V>
+static size_t kA_lds_v(int logn, int dtype) {
+    switch (logn) {
+    case 8: return dtype == 0 ? kA_lds_bytes_v<V, double, 8>() : kA_lds_bytes_v<V, float, 8>();
+    case 9: return dtype == 0 ? kA_lds_bytes_v<V, double, 9>() : kA_lds_bytes_v<V, float, 9>();
+    case 10: return dtype == 0 ? kA_lds_bytes_v<V, double, 10>() : kA_lds_bytes_v<V, float, 10>();
+    case 11: return dtype == 0 ? kA_lds_bytes_v<V, double, 11>() : kA_lds_bytes_v<V, float, 11>();
+    case 12: return dtype == 0 ? kA_lds_bytes_v<V, double, 12>() : kA_lds_bytes_v<V, float, 12>();
+    case 13: return dtype == 0 ? kA_lds_bytes_v<V, double, 13>() : kA_lds_bytes_v<V, float, 13>();
+    default: return dtype == 0 ? kA_lds_bytes_v<V, double, 14>() : kA_lds_bytes_v<V, float, 14>();
+    }
+}
+
+size_t kA_lds(int variant, int logn, int dtype) {
+    return (variant == 1 || variant == 5) ? kA_lds_v<1>(logn, dtype) : kA_lds_v<4>(logn, dtype);
 }
 
 void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes) {
@@ -1457,14 +1839,17 @@ void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* ld
 
 template <int V>
 static hipError_t prime_kA_v(int dtype) {
+    constexpr bool LOSS = !variant_traits<V>::recurrence;  // the fused loss kernel: M4 / M8
     switch (dtype) {
     case 0: {
         const hipError_t e = prime_kA_n<V, double2, 8>();
-        return e == hipSuccess ? prime_kA_loss_n<V, double2, 8>() : e;
+        if constexpr (LOSS) return e == hipSuccess ? prime_kA_loss_n<V, double2, 8>() : e;
+        return e;
     }
     case 1: {
         const hipError_t e = prime_kA_n<V, float2, 8>();
-        return e == hipSuccess ? prime_kA_loss_n<V, float2, 8>() : e;
+        if constexpr (LOSS) return e == hipSuccess ? prime_kA_loss_n<V, float2, 8>() : e;
+        return e;
     }
     case 2: return prime_kA_n<V, __half2, 8>();
     default: return prime_kA_n<V, bf16x2, 8>();
@@ -1472,13 +1857,17 @@ static hipError_t prime_kA_v(int dtype) {
 }
 
 hipError_t prime_kA(int variant, int dtype) {
-    if (variant == 4) return prime_kA_v<4>(dtype);
-    if (variant == 8) return prime_kA_v<8>(dtype);
-    return hipSuccess;
+    switch (variant) {
+    case 1: return prime_kA_v<1>(dtype);
+    case 4: return prime_kA_v<4>(dtype);
+    case 5: return prime_kA_v<5>(dtype);
+    case 8: return prime_kA_v<8>(dtype);
+    default: return hipSuccess;
+    }
 }
 
 bool kA_loss_supported(int variant, int logn, int dtype) {
-    return (dtype == 0 || dtype == 1) && kA_supported(variant, logn, dtype);
+    return (variant == 4 || variant == 8) && (dtype == 0 || dtype == 1) && kA_supported(variant, logn, dtype);
 }
 
 hipError_t launch_kA_loss(const loss_launch& a, hipStream_t st) {
@@ -1530,8 +1919,12 @@ static hipError_t launch_kA_t(const lds_launch& a, hipStream_t st) {
 
 hipError_t launch_kA(const lds_launch& a, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
-    if (a.variant == 4) return launch_kA_t<4>(a, st);
-    return launch_kA_t<8>(a, st);
+    switch (a.variant) {
+    case 1: return launch_kA_t<1>(a, st);
+    case 4: return launch_kA_t<4>(a, st);
+    case 5: return launch_kA_t<5>(a, st);
+    default: return launch_kA_t<8>(a, st);
+    }
 }
 
 }  // namespace amqft

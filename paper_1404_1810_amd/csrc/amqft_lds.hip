@@ -453,6 +453,7 @@ void describe_lds(const lds_launch& a, char* buf, size_t len) {
     size_t lds = 0;
     if (!a.generic && kA_supported(a.variant, a.logn, a.dtype)) {
         kA_shape(a.logn, a.dtype, &threads, &spw, &lds);
+        lds = kA_lds(a.variant, a.logn, a.dtype);
         snprintf(buf, len, "amqft_kA_kernel<%d, %s, %d> grid=%lld block=%d lds=%zu", a.variant, sname, a.logn,
                  (long long)((a.batch + spw - 1) / spw), threads, lds);
     } else if (!a.generic && fast_supported(a.logn, a.dtype)) {
