@@ -71,6 +71,10 @@ struct amqft_plan_s {
     bool tuned = false;
     // captured graphs
     std::vector<graph_entry> graphs;
+    // many-length plans with classes above one workgroup's LDS: those run on
+    // a second stream forked from (and joined back into) the caller's stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -276,10 +280,24 @@ amqft_status exec_many(amqft_plan p, const void* in, void* out, hipStream_t stre
         if (e != hipSuccess) return hip_fail(e);
     }
     if (!classes) return AMQFT_OK;
+    // long classes (global-memory paths) on the side stream, concurrently with
+    // the rest; every class writes only its own signals
+    const bool fork = p->side != nullptr;
+    if (fork) {
+        hipError_t e = hipEventRecord(p->ev_fork, stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+        if (e != hipSuccess) return hip_fail(e);
+    }
     for (const length_class& c : p->classes) {
         if (!c.sub) continue;
-        amqft_status st = exec_single(c.sub, in, out, stream, adjoint);
+        const bool long_class = c.sub->large || c.sub->multipass;
+        amqft_status st = exec_single(c.sub, in, out, fork && long_class ? p->side : stream, adjoint);
         if (st != AMQFT_OK) return st;
+    }
+    if (fork) {
+        hipError_t e = hipEventRecord(p->ev_join, p->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(stream, p->ev_join, 0);
+        if (e != hipSuccess) return hip_fail(e);
     }
     return AMQFT_OK;
 }
@@ -576,6 +594,18 @@ amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_
         if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
         p->ws_bytes += c.sub->ws_bytes;
     }
+    bool has_long = false, has_short = p->nitems > 0;
+    for (const length_class& c : p->classes) {
+        if (!c.sub) continue;
+        if (c.sub->large || c.sub->multipass) has_long = true;
+        else has_short = true;
+    }
+    if (has_long && has_short) {
+        e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);  // default priority
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) { amqft_plan_destroy(p); return hip_fail(e); }
+    }
     *out = p;
     return AMQFT_OK;
 }
@@ -665,6 +695,9 @@ amqft_status amqft_plan_destroy(amqft_plan p) {
         if (c.sub) amqft_plan_destroy(c.sub);
         if (c.offsets_dev) (void)hipFree(c.offsets_dev);
     }
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->side) (void)hipStreamDestroy(p->side);
     if (p->items_dev) (void)hipFree(p->items_dev);
     if (p->poffsets_dev) (void)hipFree(p->poffsets_dev);
     if (p->ktab) (void)hipFree(p->ktab);
