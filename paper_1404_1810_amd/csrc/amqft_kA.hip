@@ -687,6 +687,34 @@ __device__ __forceinline__ cx<R> shfl_dn_c(cx<R> v, int d) {
     return cx<R>{__shfl_down(v.re, d), __shfl_down(v.im, d)};
 }
 
+// lane i receives lane i - D (UP) or lane i + D inside its row of 16 lanes
+// (data-parallel-primitive moves: a VALU operation, no LDS traffic)
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <bool UP, int D, typename R>
+__device__ __forceinline__ cx<R> row_shift(cx<R> v) {
+    constexpr int CTRL = UP ? 0x110 + D : 0x100 + D;  // row_shr:D / row_shl:D
+    return cx<R>{dpp_mov<CTRL>(v.re), dpp_mov<CTRL>(v.im)};
+}
+
+// lane i receives lane i - d (UP) or i + d; ROW: every use stays inside
+// aligned rows of 16 lanes (then d <= 15 moves with DPP)
+template <bool UP, bool ROW, int d, typename R>
+__device__ __forceinline__ cx<R> lane_shift(cx<R> v) {
+    if constexpr (ROW) return row_shift<UP, d, R>(v);
+    else if constexpr (UP) return shfl_up_c(v, d);
+    else return shfl_dn_c(v, d);
+}
+
 template <int V, int SG>
 struct rec_dir {
     static constexpr bool asc = (V == 1) ? (SG == 0) : (SG != 0);
@@ -695,28 +723,19 @@ struct rec_dir {
 
 // exclusive sum of t over the lanes before (ASC) or after this one in its
 // segment of nl lanes (pos = index in the segment, segments of at most MAXL
-// consecutive lanes inside one wave); every lane of the wave must call it
+// consecutive lanes inside one wave -- inside one row of 16 lanes when
+// MAXL <= 16); every lane of the wave must call it
 template <bool ASC, int MAXL, typename R>
 __device__ __forceinline__ cx<R> seg_excl(cx<R> t, int pos, int nl) {
+    constexpr bool ROW = MAXL <= 16;
     const cx<R> z = zero<R>();
-    cx<R> w;
-    if constexpr (ASC) {
-        const cx<R> u1 = shfl_up_c(t, 1);
-        w = pos >= 1 ? u1 : z;
-    } else {
-        const cx<R> d1 = shfl_dn_c(t, 1);
-        w = pos + 1 < nl ? d1 : z;
-    }
-#pragma unroll
-    for (int d = 1; d < MAXL; d <<= 1) {
-        if constexpr (ASC) {
-            const cx<R> u = shfl_up_c(w, d);
-            if (pos >= d) w = w + u;
-        } else {
-            const cx<R> u = shfl_dn_c(w, d);
-            if (pos + d < nl) w = w + u;
-        }
-    }
+    const cx<R> s1 = lane_shift<ASC, ROW, 1, R>(t);
+    cx<R> w = (ASC ? pos >= 1 : pos + 1 < nl) ? s1 : z;
+    sfor<0, ilog2c(MAXL)>([&](auto kc) {
+        constexpr int d = 1 << decltype(kc)::value;
+        const cx<R> u = lane_shift<ASC, ROW, d, R>(w);
+        if (ASC ? pos >= d : pos + d < nl) w = w + u;
+    });
     return w;
 }
 
@@ -727,30 +746,20 @@ __device__ __forceinline__ cx<R> seg_excl(cx<R> t, int pos, int nl) {
 // pair; own = the partial sum inside the pair up to this lane.
 template <bool ASC, int MAXL, typename R>
 __device__ __forceinline__ void pair_excl(cx<R> u, int pos, int nl, cx<R>& carry, cx<R>& own) {
+    constexpr bool ROW = MAXL <= 16;
     const cx<R> z = zero<R>();
-    const cx<R> up = shfl_up_c(u, 1), dn = shfl_dn_c(u, 1);
+    const cx<R> up = lane_shift<true, ROW, 1, R>(u), dn = lane_shift<false, ROW, 1, R>(u);
     const bool odd = pos & 1, paired = nl > 1;
     const cx<R> ps = !paired ? u : odd ? up + u : u + dn;  // u(2m) + u(2m+1)
     own = paired && (ASC ? odd : !odd) ? ps : u;
     const int pm = pos >> 1, np = paired ? nl >> 1 : 1;
-    cx<R> w;
-    if constexpr (ASC) {
-        const cx<R> a = shfl_up_c(ps, 2);
-        w = pm >= 1 ? a : z;
-    } else {
-        const cx<R> a = shfl_dn_c(ps, 2);
-        w = pm + 1 < np ? a : z;
-    }
-#pragma unroll
-    for (int d = 1; 2 * d < MAXL; d <<= 1) {
-        if constexpr (ASC) {
-            const cx<R> a = shfl_up_c(w, 2 * d);
-            if (pm >= d) w = w + a;
-        } else {
-            const cx<R> a = shfl_dn_c(w, 2 * d);
-            if (pm + d < np) w = w + a;
-        }
-    }
+    const cx<R> a2 = lane_shift<ASC, ROW, 2, R>(ps);
+    cx<R> w = (ASC ? pm >= 1 : pm + 1 < np) ? a2 : z;
+    sfor<0, (ilog2c(MAXL) > 1 ? ilog2c(MAXL) - 1 : 0)>([&](auto kc) {
+        constexpr int d = 1 << decltype(kc)::value;
+        const cx<R> a = lane_shift<ASC, ROW, 2 * d, R>(w);
+        if (ASC ? pm >= d : pm + d < np) w = w + a;
+    });
     carry = w;
 }
 
