@@ -1,7 +1,9 @@
-// Skeleton-A AM-QFT (variants 4 and 8) for N = 2^8 .. 2^14 with the whole
+// Skeleton-A AM-QFT (variants 1, 4, 5, 8) for N = 2^8 .. 2^14 with the whole
 // dataflow fixed at compile time: a handful of passes over LDS, each reading
 // everything it needs, waiting at a barrier and writing, every thread
-// holding 16 complex values per pass.
+// holding 16 complex values per pass.  Further down: the fused loss/gradient
+// kernel on the same passes, and the global-memory kernels for N = 2^15 ..
+// 2^20 (variants 4 and 8) that reuse them on the rows of a larger transform.
 //
 // View of one side (DCT or DST, H = N/2 positions): after the forward levels
 // 0..l-1 of dct_ot / dst_ot the data form 2^l rows of W_l = H / 2^l slots;
@@ -23,7 +25,8 @@
 //   P3   rows of 16 slots at depth D-3: sub-blocks of 8, 4, 2, 1 points,
 //        forward and backward in registers.
 //   B_k  mirror of M_k: a thread combines one child index j of 2^r rows into
-//        2^r consecutive parent harmonics, with the +-1 neighbours M4 / M8 read.
+//        2^r consecutive parent harmonics, with the +-1 neighbours M4 / M8 read
+//        (M1 / M5: a segmented scan across the lanes of each child instead).
 //   B0   mirror of F1 (levels 2..0), both sides per thread.
 //   C0   chain D_n^F: levels 3..D-3 along each output's reflection path,
 //        levels 0..2 on an orbit of 8 harmonics, D_c and the store.
