@@ -194,7 +194,11 @@ template <int LOGN>
 struct kgeo {
     static constexpr int N = 1 << LOGN, H = N / 2, D = LOGN - 2, Q = N / 4;
     static constexpr int T = N / 16;                 // threads per signal (= depth-3 row width W3)
-    static constexpr int WG = T >= 256 ? T : 256;    // threads per workgroup
+    // threads per workgroup: one signal per workgroup from N = 4096 on; below,
+    // several signals share a workgroup of 256 threads, or of one wave for
+    // N <= 1024 (measured faster there for the fused loss and the FP64
+    // latency case, and for N = 512)
+    static constexpr int WG = T >= 256 ? T : LOGN <= 10 ? (T >= 64 ? T : 64) : 256;
     static constexpr int SPW = WG / T;               // signals per workgroup
     static constexpr int W3 = H / 8, W3P = W3 + W3 / 16;
     static constexpr int HS = H + H / 16;            // padded positions of one half
@@ -1833,7 +1837,7 @@ size_t kA_lds(int variant, int logn, int dtype) {
 }
 
 void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes) {
-    const int N = 1 << logn, T = N / 16, WG = T >= 256 ? T : 256;
+    const int N = 1 << logn, T = N / 16, WG = T >= 256 ? T : logn <= 10 ? (T >= 64 ? T : 64) : 256;
     *threads = WG;
     *signals_per_wg = WG / T;
     size_t b = 0;
