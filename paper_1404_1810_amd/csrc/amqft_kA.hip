@@ -1495,9 +1495,11 @@ hipError_t prime_kA_n() {
 //   rows   two rows (one per context) per workgroup through every level
 //          below depth 3 and back; each row -> ws1 in block layout (block a
 //          at W3 - W3 / 2^a)
-//   back   levels 2..0 for every block (B0 over global rows) -> ws2, depth 0
+//   back   levels 2..0 (B0 over global rows) for the blocks a >= 3 and the
+//          few groups of blocks 0..2 that harmonics N/16 i read -> ws2, depth 0
 //          in block layout per side (block a at H - H / 2^a)
-//   chain  chain, D_c and the store (C0 over ws2 and wsc)
+//   bchain B0 of the blocks 0..2 that a workgroup's chain threads read, into
+//          LDS; then the chain, D_c and the store (C0)
 // ---------------------------------------------------------------------------
 template <int LOGN>
 struct global_layout {
@@ -1701,12 +1703,12 @@ __global__ __launch_bounds__(256) void amqft_kL_rback(const cx<R>* __restrict__ 
     for (int e = 0; e < 8; ++e) out[e] = o[e];
 }
 
+// B0 of one position p of the depth-3 block layout (block a, index j): the
+// eight rows of each side at p - 1, p, p + 1 (neighbours outside the block
+// count as zero) give harmonics 8j .. 8j + 7 of depth-0 block a of both sides.
 template <int V, typename R, int LOGN>
-__global__ __launch_bounds__(256) void amqft_kL_back(const cx<R>* __restrict__ ws1, cx<R>* __restrict__ ws2) {
-    constexpr int N = 1 << LOGN, H = N / 2, W3 = N / 16, LW3 = ilog2c(W3);
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= W3 - 1) return;
-    const cx<R>* sig = ws1 + (long long)blockIdx.y * N;
+__device__ __forceinline__ void b0_group(const cx<R>* __restrict__ sig, int p, cx<R> (&o)[2][8]) {
+    constexpr int N = 1 << LOGN, W3 = N / 16, LW3 = ilog2c(W3);
     const int a = __clz(~(p << (32 - LW3)));  // block of position p in the row's block layout
     const int j = p - (W3 - (W3 >> a));
     const int sp = W3 >> (a + 1);
@@ -1722,29 +1724,180 @@ __global__ __launch_bounds__(256) void amqft_kL_back(const cx<R>* __restrict__ w
             ext[side][q][1] = row[p];
             ext[side][q][2] = j + 1 < sp ? lp : zero<R>();
         }
-    cx<R>* out = ws2 + (long long)blockIdx.y * N + (H - (H >> a)) + 8 * j;
-    cx<R> o[8];
-    bwd_run<V, 0, 3, R>(ext[0], o);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) out[e] = o[e];
-    bwd_run<V, 1, 3, R>(ext[1], o);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) out[H + e] = o[e];
+    bwd_run<V, 0, 3, R>(ext[0], o[0]);
+    bwd_run<V, 1, 3, R>(ext[1], o[1]);
 }
 
-template <typename S, int LOGN>
-__global__ __launch_bounds__(256) void amqft_kL_chain(const cx<typename storage<S>::R>* __restrict__ ws2,
-                                                       const cx<typename storage<S>::R>* __restrict__ wsc,
-                                                       S* __restrict__ out, long long sig0, long long batch, int flags,
-                                                       const long long* __restrict__ offsets) {
+// B0 into ws2 (depth-0 block layout per side) for the blocks a >= 3, which
+// the chain reads at folded indices from every part of the signal, and for
+// the 14 groups of blocks 0..2 that the harmonics N/16 i (thread k0 = 0 of
+// the chain) read: block 0 at harmonics 0, N/16 i - 1, N/16 i (i = 1..3) and
+// N/4 - 1; block 1 at 0, N/16 - 1, N/16, N/8 - 1; block 2 at 0, N/16 - 1.
+template <int V, typename R, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_back(const cx<R>* __restrict__ ws1, cx<R>* __restrict__ ws2) {
+    constexpr int N = 1 << LOGN, H = N / 2, W3 = N / 16, NB3 = W3 / 8 - 1, GA = N / 128;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= NB3 + 14) return;
+    int p;
+    if (i < NB3) {
+        p = W3 - W3 / 8 + i;
+    } else {
+        const int x = i - NB3;
+        const int a = x < 8 ? 0 : x < 12 ? 1 : 2;
+        const int y = x - (x < 8 ? 0 : x < 12 ? 8 : 12);
+        const int g = ((y + 1) >> 1) * GA - (y & 1);  // 0, GA - 1, GA, 2 GA - 1, 2 GA, ...
+        p = W3 - (W3 >> a) + g;
+    }
+    constexpr int LW3 = ilog2c(W3);
+    const int a = __clz(~(p << (32 - LW3)));
+    const int j = p - (W3 - (W3 >> a));
+    cx<R> o[2][8];
+    b0_group<V, R, LOGN>(ws1 + (long long)blockIdx.y * N, p, o);
+    cx<R>* out = ws2 + (long long)blockIdx.y * N + (H - (H >> a)) + 8 * j;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[e] = o[0][e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[H + e] = o[1][e];
+}
+
+// B0 for blocks 0..2 and the chain in one kernel.  Workgroup K/256 serves
+// the chain threads k0 = K .. K + 255, whose harmonics in blocks 0..2 lie in
+// seven windows of 34 groups of eight (block 0 at k0, N/8 - k0, N/8 + k0,
+// N/4 - k0; block 1 at k0, N/8 - k0; block 2 at k0; the DST side one index
+// lower); the workgroup runs B0 for those groups into LDS, then the chain
+// reads them there and blocks >= 3 and the chain values from ws2 / wsc.
+// Thread k0 = 0 (harmonics N/16 i) reads everything from ws2.
+template <typename R>
+constexpr size_t kL_bchain_lds() { return 2 * 7 * 34 * 8 * sizeof(cx<R>); }
+
+template <int V, typename S, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage<S>::R>* __restrict__ ws1,
+                                                        const cx<typename storage<S>::R>* __restrict__ ws2,
+                                                        const cx<typename storage<S>::R>* __restrict__ wsc,
+                                                        S* __restrict__ out, long long sig0, long long batch, int flags,
+                                                        const long long* __restrict__ offsets) {
     using R = typename storage<S>::R;
-    constexpr int N = 1 << LOGN, W3 = N / 16;
-    const int k0 = blockIdx.x * 256 + threadIdx.x;
+    constexpr int N = 1 << LOGN, H = N / 2, Q = N / 4, W3 = N / 16, N8 = N / 8, D = LOGN - 2;
+    constexpr int NG = 34, NWIN = 7, WS = NG * 8, NW = D - 5;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<R>(*blk)[NWIN * WS] = reinterpret_cast<cx<R>(*)[NWIN * WS]>(smem);  // [side][slot]
+    const int K = blockIdx.x * 256, tid = threadIdx.x;
     const long long sl = blockIdx.y, gs = sig0 + sl;
-    if (gs >= batch || k0 >= W3) return;
-    const long long base = uniform64(offsets ? offsets[gs] : gs * (long long)N);
+    if (gs >= batch) return;
+    // first group of window r (block 0: r = 0..3, block 1: r = 4, 5, block 2: r = 6)
+    auto wg0 = [&](int r) {
+        return (r == 0 || r == 4 || r == 6) ? K / 8 - 1
+               : (r == 1 || r == 5)         ? (N8 - K) / 8 - 33
+               : r == 2                     ? (N8 + K) / 8 - 1
+                                            : (Q - K) / 8 - 33;
+    };
+    if (tid < NWIN * NG) {
+        const int r = tid / NG;
+        const int a = r < 4 ? 0 : r < 6 ? 1 : 2;
+        const int g = wg0(r) + (tid - r * NG);
+        if (g >= 0 && g < (W3 >> (a + 1))) {
+            cx<R> o[2][8];
+            b0_group<V, R, LOGN>(ws1 + sl * N, W3 - (W3 >> a) + g, o);
+#pragma unroll
+            for (int side = 0; side < 2; ++side)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) stc(&blk[side][tid * 8 + e], o[side][e]);
+        }
+    }
+    __syncthreads();
+    const int k0 = K + tid;
+    const cx<R>* w2 = ws2 + sl * N;
+    const cx<R>* chn = wsc + sl * 16;
     cx<R> res[16];
-    c0_compute<LOGN, R, global_layout<LOGN>>(ws2 + sl * N, wsc + sl * 16, k0, res);
+    if (k0 == 0) {
+        c0_compute<LOGN, R, global_layout<LOGN>>(w2, chn, 0, res);
+    } else {
+        // harmonic k of window r, side s
+        auto lw = [&](int s, int r, int k) { return ldc(&blk[s][r * WS + k - 8 * wg0(r)]); };
+        auto gb = [](int a) { return H - (H >> a); };  // block a of side 0 in ws2
+        auto lo = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re + Dv.im, Cv.im - Dv.re}; };
+        auto hi = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re - Dv.im, Cv.im + Dv.re}; };
+        // the chain walk: folded indices and signs, as in the LDS kernel's C0
+        int ic[NW], is[NW];
+        R wc[NW], wsg[NW];
+        int kc = k0;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const int q = Q >> (3 + t);
+            const bool lt = kc < q, gt = kc > q;
+            kc = gt ? 2 * q - kc : kc;
+            ic[t] = kc;
+            wc[t] = lt ? R(1) : gt ? R(-1) : R(0);
+        }
+        int ks = k0;
+        R sgn = R(1);
+        bool done = false;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const int q = Q >> (3 + t);
+            const bool gt = ks > q, eq = ks == q;
+            const int kn = gt ? 2 * q - ks : ks;
+            is[t] = done ? 1 : kn;
+            wsg[t] = done ? R(0) : sgn;
+            sgn = (!done && gt) ? -sgn : sgn;
+            done = done || eq;
+            ks = kn;
+        }
+        const int e8 = done ? 0 : ks;
+        const R wd = done ? R(0) : sgn;
+        cx<R> accs = ldc(chn + 8 + e8) * wd;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const cx<R> o = ldc(w2 + H + gb(3 + t) + is[t] - 1);
+            accs = cx<R>{accs.re + wsg[t] * o.re, accs.im + wsg[t] * o.im};
+        }
+        cx<R> accc = ldc(chn + kc);
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const cx<R> o = ldc(w2 + gb(3 + t) + ic[t]);
+            accc = cx<R>{accc.re + wc[t] * o.re, accc.im + wc[t] * o.im};
+        }
+        const int kA = k0, kB = N8 - k0, kC = kA + N8, kD = kB + N8;
+        const cx<R> oc2 = lw(0, 6, kA);
+        const cx<R> c2a = accc + oc2, c2b = accc - oc2;
+        const cx<R> o1a = lw(0, 4, kA), o1b = lw(0, 5, kB);
+        const cx<R> c1[4] = {c2a + o1a, c2b + o1b, c2b - o1b, c2a - o1a};
+        const cx<R> o0[4] = {lw(0, 0, kA), lw(0, 1, kB), lw(0, 2, kC), lw(0, 3, kD)};
+        cx<R> C[8];  // E_0 at kA, kB, kC, kD, H-kD, H-kC, H-kB, H-kA
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            C[i] = c1[i] + o0[i];
+            C[7 - i] = c1[i] - o0[i];
+        }
+        const cx<R> os2 = lw(1, 6, kA - 1);
+        const cx<R> s2a = os2 + accs, s2b = os2 - accs;
+        const cx<R> p1a = lw(1, 4, kA - 1), p1b = lw(1, 5, kB - 1);
+        const cx<R> s1[4] = {p1a + s2a, p1b + s2b, p1b - s2b, p1a - s2a};
+        const cx<R> q0[4] = {lw(1, 0, kA - 1), lw(1, 1, kB - 1), lw(1, 2, kC - 1), lw(1, 3, kD - 1)};
+        cx<R> Dd[8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            Dd[i] = q0[i] + s1[i];
+            Dd[7 - i] = q0[i] - s1[i];
+        }
+        res[0] = lo(C[0], Dd[0]);
+        res[1] = lo(C[2], Dd[2]);
+        res[2] = lo(C[4], Dd[4]);
+        res[3] = lo(C[6], Dd[6]);
+        res[4] = hi(C[7], Dd[7]);
+        res[5] = hi(C[5], Dd[5]);
+        res[6] = hi(C[3], Dd[3]);
+        res[7] = hi(C[1], Dd[1]);
+        res[8] = lo(C[1], Dd[1]);
+        res[9] = lo(C[3], Dd[3]);
+        res[10] = lo(C[5], Dd[5]);
+        res[11] = lo(C[7], Dd[7]);
+        res[12] = hi(C[6], Dd[6]);
+        res[13] = hi(C[4], Dd[4]);
+        res[14] = hi(C[2], Dd[2]);
+        res[15] = hi(C[0], Dd[0]);
+    }
+    const long long base = uniform64(offsets ? offsets[gs] : gs * (long long)N);
     c0_store<LOGN, S, R, true>(out + base, k0, res, (flags & 2) != 0);
 }
 
@@ -1775,10 +1928,11 @@ hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
             hipLaunchKernelGGL((amqft_kL_rback<V, R, LOGN>), dim3(W6 / 256, 16, (unsigned)nb), dim3(256), 0, st,
                                static_cast<const cx<R>*>(ws2), ws1);
         }
-        hipLaunchKernelGGL((amqft_kL_back<V, R, LOGN>), gw, dim3(256), 0, st, static_cast<const cx<R>*>(ws1), ws2);
-        hipLaunchKernelGGL((amqft_kL_chain<S, LOGN>), gw, dim3(256), 0, st, static_cast<const cx<R>*>(ws2),
-                           static_cast<const cx<R>*>(wsc), static_cast<S*>(a.out), s0, (long long)a.batch, flags,
-                           static_cast<const long long*>(a.offsets));
+        const dim3 gb((W3 / 8 - 1 + 14 + 255) / 256, (unsigned)nb);
+        hipLaunchKernelGGL((amqft_kL_back<V, R, LOGN>), gb, dim3(256), 0, st, static_cast<const cx<R>*>(ws1), ws2);
+        hipLaunchKernelGGL((amqft_kL_bchain<V, S, LOGN>), gw, dim3(256), kL_bchain_lds<R>(), st, static_cast<const cx<R>*>(ws1),
+                           static_cast<const cx<R>*>(ws2), static_cast<const cx<R>*>(wsc), static_cast<S*>(a.out), s0,
+                           (long long)a.batch, flags, static_cast<const long long*>(a.offsets));
     }
     return hipGetLastError();
 }
