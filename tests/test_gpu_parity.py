@@ -123,6 +123,34 @@ def test_deterministic():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("n", [2048, 8192, 1 << 15])
+def test_fp64_repeated_launches_identical(n):
+    """FP64 results of 40 launches on the same input agree bit for bit and
+    with the oracle.  Guards the 16-byte output stores: a store whose data
+    registers were overwritten by the next instruction wrote the low word of
+    a real part wrong in a few launches out of ten (lanes 12..15 of 16-lane
+    rows), an error of 1e-7 relative that a single launch rarely shows."""
+    from paper_1404_1810_amd import _lib
+    api = _api()
+    batch = 64 if n <= 8192 else 4
+    _say("fp64 repeated launches n", n, "batch", batch)
+    xn = inputs.complex_uniform(2000 + n, batch, n)
+    ref = truth(xn, 4)
+    x = torch.from_numpy(xn).cuda()
+    plan = api.Plan(n, batch, 4, _lib.C128, 0)
+    first = torch.empty_like(x)
+    plan.exec(x, out=first)
+    y = torch.empty_like(x)
+    for it in range(40):
+        y.fill_(0)
+        plan.exec(x, out=y)
+        torch.cuda.synchronize()
+        assert torch.equal(y, first), (n, it)
+    e = rel(first.cpu().numpy(), ref)
+    assert e <= 1e-12, (n, e)
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_multipass_forced_small(variant):
     """The multi-pass path (global levels + LDS sub-blocks + tail) forced at
