@@ -119,3 +119,34 @@ def test_single_plan_graph_replay():
         api.exec_graph(plan, x, y)
         torch.cuda.synchronize()
         assert torch.equal(y, eager)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_uneven_long_classes_only(dtype):
+    """Only lengths above one workgroup's LDS (no persistent launch, no side
+    stream): 2^15 and 2^16 signals interleaved, FP32 and FP64, forward and
+    adjoint against the oracle."""
+    from paper_1404_1810_amd import api, _lib
+    ks = [15, 16, 15, 16, 15]
+    lengths, offsets = _layout(ks, gap=5)
+    _say("uneven long classes", dtype, "points", int(offsets[-1]))
+    rng = np.random.default_rng(21)
+    buf = rng.standard_normal(int(offsets[-1])) + 1j * rng.standard_normal(int(offsets[-1]))
+    f64 = dtype == "c128"
+    buf = buf.astype(np.complex128 if f64 else np.complex64)
+    plan = api.ManyPlan(lengths, offsets, 4, _lib.C128 if f64 else _lib.C64)
+    x = torch.from_numpy(buf).cuda()
+    for adjoint in (False, True):
+        y = torch.full_like(x, complex(7.0, 7.0))
+        plan.exec(x, out=y, adjoint=adjoint)
+        got = y.cpu().numpy()
+        for i, (n, o) in enumerate(zip(lengths, offsets[:-1])):
+            seg = buf[o:o + n]
+            src = np.conj(seg) if adjoint else seg
+            ref = truth(src[None, :], 4)[0]
+            if adjoint:
+                ref = np.conj(ref)
+            e = rel(got[o:o + n], ref)
+            assert e <= bound(4, f64, seg[None, :], ref[None, :]), (i, n, adjoint, e)
+            assert np.all(got[o + n:offsets[i + 1]] == 7 + 7j)
