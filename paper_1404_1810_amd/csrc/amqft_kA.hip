@@ -1740,9 +1740,9 @@ __device__ __forceinline__ void b0_group(const cx<R>* __restrict__ sig, int p, c
 // the chain) read: block 0 at harmonics 0, N/16 i - 1, N/16 i (i = 1..3) and
 // N/4 - 1; block 1 at 0, N/16 - 1, N/16, N/8 - 1; block 2 at 0, N/16 - 1.
 template <int V, typename R, int LOGN>
-__global__ __launch_bounds__(256) void amqft_kL_back(const cx<R>* __restrict__ ws1, cx<R>* __restrict__ ws2) {
+__global__ __launch_bounds__(64) void amqft_kL_back(const cx<R>* __restrict__ ws1, cx<R>* __restrict__ ws2) {
     constexpr int N = 1 << LOGN, H = N / 2, W3 = N / 16, NB3 = W3 / 8 - 1, GA = N / 128;
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.x * 64 + threadIdx.x;  // one-wave workgroups: few threads per signal
     if (i >= NB3 + 14) return;
     int p;
     if (i < NB3) {
@@ -1934,8 +1934,8 @@ hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
             hipLaunchKernelGGL((amqft_kL_rback<V, R, LOGN>), dim3(W6 / 256, 16, (unsigned)nb), dim3(256), 0, st,
                                static_cast<const cx<R>*>(ws2), ws1);
         }
-        const dim3 gb((W3 / 8 - 1 + 14 + 255) / 256, (unsigned)nb);
-        hipLaunchKernelGGL((amqft_kL_back<V, R, LOGN>), gb, dim3(256), 0, st, static_cast<const cx<R>*>(ws1), ws2);
+        const dim3 gb((W3 / 8 - 1 + 14 + 63) / 64, (unsigned)nb);
+        hipLaunchKernelGGL((amqft_kL_back<V, R, LOGN>), gb, dim3(64), 0, st, static_cast<const cx<R>*>(ws1), ws2);
         hipLaunchKernelGGL((amqft_kL_bchain<V, S, LOGN>), gw, dim3(256), kL_bchain_lds<R>(), st, static_cast<const cx<R>*>(ws1),
                            static_cast<const cx<R>*>(ws2), static_cast<const cx<R>*>(wsc), static_cast<S*>(a.out), s0,
                            (long long)a.batch, flags, static_cast<const long long*>(a.offsets));
