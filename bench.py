@@ -46,13 +46,51 @@ def flops_5nlogn(n: int, batch: int) -> float:
     return 5.0 * n * math.log2(n) * batch
 
 
-def time_launches(fn, steps: int, warmup: int, stream):
-    """Average duration of each launch (events on the launch stream) and the
-    wall time of the whole timed region."""
+# Warm-up floor applied before every timed workload, whatever --warmup says:
+# the GPU's clocks take some tens of milliseconds of back-to-back work to
+# settle, so launches continue until at least WARMUP_FLOOR_MS of wall time has
+# passed and the median launch time of the last window of launches agrees
+# with that of the window before within WARMUP_TOL (or WARMUP_CAP_MS passed).
+WARMUP_FLOOR_MS = 200.0
+WARMUP_TOL = 0.02
+WARMUP_WINDOW = 10
+WARMUP_CAP_MS = 3000.0
+
+
+def settle(fn, stream):
+    """Run fn back to back until its launch time is steady; returns the
+    warm-up's wall time in ms."""
     import torch
+    t0 = time.perf_counter()
+    prev = None
+    while True:
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(WARMUP_WINDOW)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ts = sorted(a.elapsed_time(b) for a, b in evs)
+        med = ts[len(ts) // 2]
+        spent = (time.perf_counter() - t0) * 1e3
+        steady = prev is not None and abs(med - prev) <= WARMUP_TOL * prev
+        if (spent >= WARMUP_FLOOR_MS and steady) or spent >= WARMUP_CAP_MS:
+            return spent
+        prev = med
+
+
+def time_launches(fn, steps: int, warmup: int, stream, floor: bool = True):
+    """Average duration of each launch (events on the launch stream) and the
+    wall time of the whole timed region, after `warmup` untimed launches and
+    the time-based warm-up floor (settle; floor=False only for the long
+    reference loops, whose single launch already runs for over 100 ms)."""
+    import torch
+    t0 = time.perf_counter()
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    warm_ms = settle(fn, stream) if floor else (time.perf_counter() - t0) * 1e3
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -68,7 +106,7 @@ def time_launches(fn, steps: int, warmup: int, stream):
     total = t0.elapsed_time(t1)
     per.sort()
     return {"avg_ms": sum(per) / len(per), "median_ms": per[len(per) // 2], "min_ms": per[0],
-            "total_ms": total, "ms_per_step": total / steps}
+            "total_ms": total, "ms_per_step": total / steps, "warmup_ms": warm_ms}
 
 
 def kernel_family(desc: str) -> str:
@@ -150,8 +188,9 @@ def ingest_pmc(args, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
     print(json.dumps(rec))
 
 
-def cpu_baseline(x_np, n: int, variant: int, target_s: float = 12.0):
-    """Time the FP64 oracle on the first signals of the same workload."""
+def cpu_baseline(x_np, n: int, variant: int, target_s: float = 12.0, single_s: float = 4.0):
+    """Time the FP64 oracle on the first signals of the same workload: one
+    thread per host core across signals, and a single thread."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -161,6 +200,13 @@ def cpu_baseline(x_np, n: int, variant: int, target_s: float = 12.0):
     t = time.perf_counter()
     oracle.cdft(x_np[:2].astype(np.complex128), variant)
     per_sig = max((time.perf_counter() - t) / 2, 1e-6)
+    # single thread: whole signals until about single_s seconds
+    n1 = max(1, min(len(x_np), int(single_s / per_sig)))
+    x1 = x_np[:n1].astype(np.complex128)
+    t = time.perf_counter()
+    oracle.cdft(x1, variant)
+    el1 = time.perf_counter() - t
+    one = {"value": flops_5nlogn(n, n1) / el1 / 1e9, "sample": "first %d signals, %.1f s on 1 thread" % (n1, el1)}
     want = max(cores, int(target_s * cores / per_sig))  # signal transforms for ~target_s of wall time
     sample = min(want, len(x_np))
     passes = max(1, min(20, (want + sample - 1) // sample))  # the sample again when it is short
@@ -178,7 +224,8 @@ def cpu_baseline(x_np, n: int, variant: int, target_s: float = 12.0):
     el = time.perf_counter() - t
     return {"value": flops_5nlogn(n, sample * passes) / el / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
             "sample": "first %d signals of the workload x %d passes (N=%d, FP64 recursive oracle, variant %d), "
-                      "%.1f s wall on %d threads" % (sample, passes, n, variant, el, cores)}
+                      "%.1f s wall on %d threads" % (sample, passes, n, variant, el, cores),
+            "value_1thread": round(one["value"], 4), "sample_1thread": one["sample"]}
 
 
 
@@ -278,7 +325,7 @@ def bench_uneven(args, stream):
         for i, pl in enumerate(singles):
             o, n = int(offsets[i]), int(lengths[i])
             pl.exec(x[o:o + n], out=y3[o:o + n])
-    b1 = time_launches(per_signal, 2, 1, stream)
+    b1 = time_launches(per_signal, 2, 1, stream, floor=False)
     torch.cuda.synchronize()
     yf = y.cpu().numpy()
     # accuracy: fused vs plain (same relations, different kernels) and vs the
@@ -324,6 +371,7 @@ def bench_grad(args, stream):
         scrub.fill_(1)
     for _ in range(args.warmup):
         plan.power_loss_grad(x, w)
+    settle(lambda: plan.power_loss_grad(x, w), stream)
     fused = _event_time(lambda: plan.power_loss_grad(x, w), args.steps, stream, do_scrub)
 
     def autograd_step():
@@ -334,6 +382,7 @@ def bench_grad(args, stream):
         return xr.grad
     for _ in range(args.warmup):
         autograd_step()
+    settle(autograd_step, stream)
     auto = _event_time(autograd_step, max(3, args.steps // 2), stream, do_scrub)
     loss, g = plan.power_loss_grad(x, w)
     torch.cuda.synchronize()
@@ -395,7 +444,7 @@ def bench_precision(args, stream):
     res = {}
     for v in range(1, 9):
         plan = api.Plan(n, B, v, _lib.C32H, _lib.FLAG_ONTHEFLY_CONSTANTS)
-        r = time_launches(lambda: plan.exec(xh, out=yh), max(3, min(20, args.steps // 10)), 2, stream)
+        r = time_launches(lambda: plan.exec(xh, out=yh), max(3, min(20, args.steps // 10)), 2, stream, floor=False)
         got = yh[sample].float().cpu().numpy()
         got = got[..., 0].astype(np.float64) + 1j * got[..., 1].astype(np.float64)
         nonfinite = int((~np.isfinite(got)).sum())
@@ -412,10 +461,9 @@ def bench_precision(args, stream):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # the GPU's clocks settle only after some 50 back-to-back launches of the
-    # headline workload (about 15 ms), so the default warm-up covers that
+    # untimed launches before the time-based warm-up floor of every workload
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--variant", type=int, default=4)
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--n", type=int, default=4096)
@@ -517,6 +565,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(head["ms_per_step"], 5),
+        "warmup_ms": round(head["warmup_ms"], 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

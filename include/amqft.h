@@ -73,16 +73,23 @@ enum {
     AMQFT_FLAG_ONTHEFLY_CONSTANTS = 1u,
     /* Do not consult the tuning table; use the default launch shape. */
     AMQFT_FLAG_NO_AUTOTUNE = 2u,
-    /* Use the multi-pass (global-memory) path even when a signal fits LDS. */
-    AMQFT_FLAG_FORCE_MULTIPASS = 4u
+    /* Use the multi-pass (global-memory) path even when a signal fits LDS.
+     * For tests of that path at sizes where every variant is accurate. */
+    AMQFT_FLAG_FORCE_MULTIPASS = 4u,
+    /* Use the large-N path of variants 4 and 8 (top levels, rows, back
+     * levels and chain over a global workspace) even when a signal fits
+     * LDS: from N = 2^11, FP64 and FP32 storage only (AMQFT_ERR_UNSUPPORTED
+     * otherwise, and together with AMQFT_FLAG_FORCE_MULTIPASS).  For tests of
+     * that path at sizes where every variant is accurate. */
+    AMQFT_FLAG_FORCE_LARGE = 8u
 };
 
 /* Environment (read at plan creation):
  *   AMQFT_TUNE_CACHE   path of a JSON-lines file that keeps autotuned launch
  *                      shapes across processes (see amqft_plan_create_many);
- *   AMQFT_LARGE_WS_MB  size in MiB of each of the two workspace buffers of
- *                      plans for N above one workgroup's LDS (default 128;
- *                      signals run in chunks that fit them). */
+ *   AMQFT_LARGE_WS_MB  size in MiB (1 .. 2^20) of each of the two workspace
+ *                      buffers of the large-N plans of variants 4 and 8
+ *                      (default 128; signals run in chunks that fit them). */
 
 /* Largest supported log2(N). */
 #define AMQFT_MAX_LOG2N 24
@@ -103,8 +110,14 @@ amqft_status amqft_plan_create(amqft_plan *out, int64_t n, int64_t batch,
  * element offsets_host[i]; offsets_host has count+1 entries, is
  * non-decreasing, and offsets_host[i+1] - offsets_host[i] >= lengths_host[i]
  * (signals must not overlap).  Both arrays are host memory and are copied
- * into the plan.  The plan builds a cost-sorted work list and executes all
- * signals in one persistent launch. */
+ * into the plan.  Execution: the short lengths (up to 2^7 for variants 1, 4,
+ * 5 and 8, up to 2^12 for the others) run in one persistent launch over a
+ * work list sorted longest first; every longer length runs as one batched
+ * launch sequence per length class over the same buffer (the classes that
+ * need a global workspace on a second stream forked from, and joined back
+ * into, `stream`).  The first out-of-place execution autotunes the
+ * persistent grid and the multi-pass sub-block sizes (synchronising
+ * `stream`); an in-place execution before it runs the default shapes. */
 amqft_status amqft_plan_create_many(amqft_plan *out, int64_t count,
                                     const int64_t *lengths_host,
                                     const int64_t *offsets_host,
@@ -152,11 +165,15 @@ amqft_status amqft_plan_describe(amqft_plan plan, char *buf, size_t len);
 /* Bytes of device workspace owned by the plan (0 when none). */
 amqft_status amqft_plan_workspace_size(amqft_plan plan, size_t *bytes);
 
-/* Copy the plan's constant table for length n (n/4 entries, in FP64, as the
- * kernels read them after rounding to the working precision) into host
+/* Copy the plan's constant table for length n (n/4 entries, widened to
+ * FP64 from the working precision the kernels read them in) into host
  * memory table_host[0 .. n/4).  Entry p holds f(2 pi p / n) for the
  * variant's family f in {2cos, 1/(2cos), 2sin, 1/(2sin)} (Sec. 7.1); entry 0
- * is unused.  For tests of the constant generation. */
+ * is unused.  Without AMQFT_FLAG_ONTHEFLY_CONSTANTS these are the host
+ * values (long double, rounded once to the working precision); with it, the
+ * values the device generated in FP64 (the same ones the LDS-resident
+ * kernels generate per workgroup), read back with a synchronous copy
+ * (AMQFT_ERR_HIP if it fails).  For tests of the constant generation. */
 amqft_status amqft_plan_constants(amqft_plan plan, int64_t n, double *table_host,
                                   int64_t entries);
 

@@ -17,6 +17,7 @@ OK, ERR_INVALID_ARG, ERR_NOT_POW2, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP = range(6
 FLAG_ONTHEFLY_CONSTANTS = 1
 FLAG_NO_AUTOTUNE = 2
 FLAG_FORCE_MULTIPASS = 4
+FLAG_FORCE_LARGE = 8
 
 #: every function the header declares, with its ctypes signature
 SIGNATURES = {

@@ -84,6 +84,8 @@ class Plan:
         self._check_tensor(x, "input")
         y = torch.empty_like(x) if out is None else out
         self._check_tensor(y, "output")
+        if y.device != x.device:
+            raise ValueError("output is on %s, input on %s" % (y.device, x.device))
         fn = _lib.load().amqft_exec_adjoint if adjoint else _lib.load().amqft_exec
         _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                       _stream_handle(x.device)), "amqft_exec" + ("_adjoint" if adjoint else ""))
@@ -102,6 +104,11 @@ class Plan:
 
     def describe(self) -> str:
         return _describe(self._h)
+
+    def workspace_bytes(self) -> int:
+        sz = ctypes.c_size_t()
+        _lib.check(_lib.load().amqft_plan_workspace_size(self._h, ctypes.byref(sz)), "workspace_size")
+        return int(sz.value)
 
     def constants(self, n: int | None = None):
         import numpy as np
@@ -122,13 +129,19 @@ _plan_cache: dict = {}
 
 
 def get_plan(n: int, batch: int, variant: int, dtype: int, flags: int = 0, device=None) -> Plan:
+    """Cached plan per shape and device.  A plan that owns a workspace may not
+    run on two streams at once, so those are cached per stream as well."""
     dev = torch.cuda.current_device() if device is None else torch.device(device).index
     key = (n, batch, variant, dtype, flags, dev)
     p = _plan_cache.get(key)
+    if p is not None:
+        return p
+    skey = key + (torch.cuda.current_stream(dev).cuda_stream,)
+    p = _plan_cache.get(skey)
     if p is None:
         with torch.cuda.device(dev):
             p = Plan(n, batch, variant, dtype, flags)
-        _plan_cache[key] = p
+        _plan_cache[skey if p.workspace_bytes() > 0 else key] = p
     return p
 
 
@@ -223,14 +236,25 @@ class ManyPlan:
         _lib.check(_lib.load().amqft_plan_workspace_size(self._h, ctypes.byref(sz)), "workspace_size")
         return int(sz.value)
 
+    def _check_buffer(self, t: torch.Tensor, name: str):
+        if not t.is_cuda:
+            raise ValueError("%s must be a GPU tensor (the AM-QFT path has no CPU fallback)" % name)
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        dt = _DTYPES.get(t.dtype)
+        if dt != self.dtype:
+            raise ValueError("%s has dtype %s, the plan %d" % (name, t.dtype, self.dtype))
+        npts = t.numel() // (2 if dt in (_lib.C32H, _lib.C32B) else 1)
+        if npts < self.total:
+            raise ValueError("%s holds %d points, the plan's offsets reach %d" % (name, npts, self.total))
+
     def exec(self, x: torch.Tensor, out: torch.Tensor | None = None, adjoint: bool = False,
              graph: bool = False) -> torch.Tensor:
-        if not x.is_cuda or not x.is_contiguous():
-            raise ValueError("input must be a contiguous GPU tensor")
-        dt = _DTYPES.get(x.dtype)
-        npts = x.numel() // (2 if dt in (_lib.C32H, _lib.C32B) else 1)
-        if dt != self.dtype or npts < self.total:
-            raise ValueError("buffer does not match the plan")
+        self._check_buffer(x, "input")
+        if out is not None:
+            self._check_buffer(out, "output")
+            if out.device != x.device:
+                raise ValueError("output is on %s, input on %s" % (out.device, x.device))
         y = torch.empty_like(x) if out is None else out
         lib = _lib.load()
         st = _stream_handle(x.device)

@@ -83,12 +83,15 @@ thread_local std::string g_hip_error;
 
 amqft_status hip_fail(hipError_t e) {
     g_hip_error = hipGetErrorString(e);
+    (void)hipGetLastError();  // a failed allocation must not resurface at the next launch check
     return e == hipErrorOutOfMemory ? AMQFT_ERR_ALLOC : AMQFT_ERR_HIP;
 }
 
 bool valid_variant(int v) { return v >= 1 && v <= 8; }
 bool valid_dtype(int t) { return t >= 0 && t <= 3; }
-constexpr unsigned kAllFlags = AMQFT_FLAG_ONTHEFLY_CONSTANTS | AMQFT_FLAG_NO_AUTOTUNE | AMQFT_FLAG_FORCE_MULTIPASS;
+constexpr unsigned kAllFlags = AMQFT_FLAG_ONTHEFLY_CONSTANTS | AMQFT_FLAG_NO_AUTOTUNE | AMQFT_FLAG_FORCE_MULTIPASS |
+                               AMQFT_FLAG_FORCE_LARGE;
+constexpr unsigned kForceFlags = AMQFT_FLAG_FORCE_MULTIPASS | AMQFT_FLAG_FORCE_LARGE;
 
 int log2_exact(int64_t n) {
     if (n < 1 || (n & (n - 1)) != 0) return -1;
@@ -330,8 +333,11 @@ amqft_status time_it(F fn, hipStream_t s, float* ms) {
 // buffers hold a valid result whichever candidate ran last.  Results are
 // cached per process and, with AMQFT_TUNE_CACHE set, in that file.
 amqft_status autotune(amqft_plan p, const void* in, void* out, hipStream_t user, bool adjoint) {
-    p->tuned = true;
-    if ((p->flags & AMQFT_FLAG_NO_AUTOTUNE) || in == out) return AMQFT_OK;
+    if (p->flags & AMQFT_FLAG_NO_AUTOTUNE) {
+        p->tuned = true;
+        return AMQFT_OK;
+    }
+    if (in == out) return AMQFT_OK;  // tuning runs overwrite the output: wait for an out-of-place call
     hipError_t e = hipStreamSynchronize(user);
     if (e != hipSuccess) return hip_fail(e);
     hipStream_t s;
@@ -391,6 +397,7 @@ amqft_status autotune(amqft_plan p, const void* in, void* out, hipStream_t user,
     }
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
+    if (st == AMQFT_OK) p->tuned = true;
     return st;
 }
 
@@ -411,7 +418,8 @@ amqft_status exec_common(amqft_plan p, const void* in, void* out, void* stream, 
 
 amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int variant, int dtype, unsigned flags) {
     const int logn = log2_exact(n);
-    const bool mp = logn > max_lds_log2(dtype) || (flags & AMQFT_FLAG_FORCE_MULTIPASS);
+    const bool force_large = (flags & AMQFT_FLAG_FORCE_LARGE) != 0;
+    const bool mp = logn > max_lds_log2(dtype) || (flags & kForceFlags);
     amqft_plan_s* p = new (std::nothrow) amqft_plan_s();
     if (!p) return AMQFT_ERR_ALLOC;
     p->variant = variant;
@@ -432,14 +440,15 @@ amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int varian
         if (e != hipSuccess) st = hip_fail(e);
     }
     if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
-    if (mp && !(flags & AMQFT_FLAG_FORCE_MULTIPASS) && kL_supported(variant, logn, dtype)) {
+    if (mp && !(flags & AMQFT_FLAG_FORCE_MULTIPASS) &&
+        (force_large ? kL_supported_forced(variant, logn, dtype) : kL_supported(variant, logn, dtype))) {
         // workspaces sized so that both stay within the last-level cache
         p->large = true;
         const size_t per = kL_ws_bytes_per_signal(logn, dtype);
         size_t cap = size_t(128) << 20;  // bytes per workspace buffer
         if (const char* env = getenv("AMQFT_LARGE_WS_MB")) {
             const long mb = atol(env);
-            if (mb >= 1 && mb <= 8192) cap = size_t(mb) << 20;
+            if (mb >= 1 && mb <= (1l << 20)) cap = size_t(mb) << 20;
         }
         p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per)));
         const size_t chain = (size_t)p->chunk * 16 * (dtype == AMQFT_C128 ? 16 : 8);
@@ -495,7 +504,10 @@ amqft_status amqft_plan_create(amqft_plan* out, int64_t n, int64_t batch, amqft_
     const int logn = log2_exact(n);
     if (logn < 0) return AMQFT_ERR_NOT_POW2;
     if (logn > AMQFT_MAX_LOG2N) return AMQFT_ERR_UNSUPPORTED;
-    const bool mp = logn > max_lds_log2((int)dtype) || (flags & AMQFT_FLAG_FORCE_MULTIPASS);
+    if ((flags & kForceFlags) == kForceFlags) return AMQFT_ERR_UNSUPPORTED;
+    if ((flags & AMQFT_FLAG_FORCE_LARGE) && !kL_supported_forced((int)variant, logn, (int)dtype))
+        return AMQFT_ERR_UNSUPPORTED;
+    const bool mp = logn > max_lds_log2((int)dtype) || (flags & kForceFlags);
     if (mp && logn < 5) return AMQFT_ERR_UNSUPPORTED;  // multi-pass needs a block of at least 8 points
     if (batch > (int64_t(1) << 40)) return AMQFT_ERR_UNSUPPORTED;
     return create_single(out, n, batch, (int)variant, (int)dtype, flags);
@@ -524,13 +536,19 @@ amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_
     if (!p) return AMQFT_ERR_ALLOC;
     p->variant = (int)variant;
     p->dtype = (int)dtype;
-    p->flags = flags & ~(unsigned)AMQFT_FLAG_FORCE_MULTIPASS;
+    p->flags = flags & ~kForceFlags;
     p->many = true;
     p->count = count;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) { delete p; return hip_fail(e); }
     amqft_status st = build_constants(p, maxlog);
     if (st == AMQFT_OK) st = prime((int)variant, (int)dtype);
+    if (st == AMQFT_OK && (flags & AMQFT_FLAG_ONTHEFLY_CONSTANTS) && maxlog >= 2) {
+        // the same FP64 device values the persistent kernel generates per workgroup
+        e = fill_table_device(p->ktab, (int)variant, (int)dtype, p->ktab_log2n, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) st = hip_fail(e);
+    }
     if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
 
     // group the signals by length
@@ -744,7 +762,24 @@ amqft_status amqft_plan_constants(amqft_plan p, int64_t n, double* table_host, i
     if (logn < 2 || logn > p->ktab_log2n) return AMQFT_ERR_INVALID_ARG;
     if (entries < n / 4) return AMQFT_ERR_INVALID_ARG;
     const int shift = p->ktab_log2n - logn;
-    for (int64_t i = 0; i < n / 4; ++i) table_host[i] = p->ktab_host[(size_t)(i << shift)];
+    if (!(p->flags & AMQFT_FLAG_ONTHEFLY_CONSTANTS)) {
+        for (int64_t i = 0; i < n / 4; ++i) table_host[i] = p->ktab_host[(size_t)(i << shift)];
+        return AMQFT_OK;
+    }
+    // generated on the device: copy the table back as the kernels read it
+    const size_t q = size_t(1) << (p->ktab_log2n - 2);
+    const bool f64 = p->dtype == AMQFT_C128;
+    std::vector<double> td;
+    std::vector<float> tf;
+    if (f64) td.resize(q);
+    else tf.resize(q);
+    hipError_t e = hipMemcpy(f64 ? (void*)td.data() : (void*)tf.data(), p->ktab, q * (f64 ? sizeof(double) : sizeof(float)),
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    for (int64_t i = 0; i < n / 4; ++i) {
+        const size_t j = (size_t)(i << shift);
+        table_host[i] = f64 ? td[j] : (double)tf[j];
+    }
     return AMQFT_OK;
 }
 

@@ -76,7 +76,7 @@ hipError_t prime_kA(int variant, int dtype);
 void kA_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
 // dynamic LDS bytes of the compile-time kernel for one variant
 size_t kA_lds(int variant, int logn, int dtype);
-// N = 2^15 .. 2^17 (FP64 to 2^16), variants 4 and 8: four kernels over a
+// N = 2^15 .. 2^20 (FP64 2^14 .. 2^16), variants 4 and 8: four kernels over a
 // global workspace (top levels, rows through the kA kernels, back levels,
 // chain); signals run in chunks of `chunk`.
 struct kl_launch {
@@ -92,6 +92,8 @@ struct kl_launch {
     const void* offsets = nullptr;
 };
 bool kL_supported(int variant, int logn, int dtype);
+// sizes a plan may force onto that path (from 2^11; tests)
+bool kL_supported_forced(int variant, int logn, int dtype);
 size_t kL_ws_bytes_per_signal(int logn, int dtype);
 hipError_t prime_kL(int variant, int dtype);
 hipError_t launch_kL(const kl_launch& a, hipStream_t stream);

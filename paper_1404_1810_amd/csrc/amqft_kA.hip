@@ -1082,7 +1082,10 @@ __device__ __forceinline__ void c0_compute(const cx<R>* w, const cx<R>* chn, int
             const int q = Q >> (3 + t);
             const bool lt = kc < q, gt = kc > q;
             kc = gt ? 2 * q - kc : kc;
-            ic[t] = kc;
+            // harmonic q of a level has no block term (weight 0); its read
+            // goes to index 0 of the block, so that it never touches the
+            // slot past the block's end (unwritten in a global workspace)
+            ic[t] = lt || gt ? kc : 0;
             wc[t] = lt ? R(1) : gt ? R(-1) : R(0);
         }
         int ks = k0;
@@ -1560,7 +1563,11 @@ __global__ __launch_bounds__(kgeo<LOGN - DEP>::WG) void amqft_kL_rows(cx<R>* __r
     R* kf = kt + G::Q;
     cx<R>* wall = reinterpret_cast<cx<R>*>(smem + (G::Q + G::KF_ALLOC) * sizeof(R));
     const int tid = threadIdx.x;
-    const int P = blockIdx.x;  // path of the row pair
+    // rows shorter than 2^12 points share a workgroup, as signals do in the
+    // LDS kernel: slot fs of the workgroup takes the row pair of path P
+    const int fs = tid / G::T, m0 = tid - fs * G::T;
+    const int P = blockIdx.x * G::SPW + fs;  // path of the row pair
+    cx<R>* w = wall + fs * G::SL;
     cx<R>* sig = ws1 + (long long)blockIdx.y * (1 << LOGN);
     // half hh (= context) holds the row of side hh ^ parity(P) (depth 3) or
     // the row of context hh (depth 6)
@@ -1568,7 +1575,6 @@ __global__ __launch_bounds__(kgeo<LOGN - DEP>::WG) void amqft_kL_rows(cx<R>* __r
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh)
         row[hh] = DEP == 3 ? sig + ((hh ^ (SW ? par(P) : 0)) * 8 + P) * W3 : sig + (2 * P + hh) * W3;
-    const int m0 = tid;
     cx<R> cd[2][8];
     if (m0 > 0) {
 #pragma unroll
@@ -1591,7 +1597,7 @@ __global__ __launch_bounds__(kgeo<LOGN - DEP>::WG) void amqft_kL_rows(cx<R>* __r
         f1_levels<V, LR, R>(kt, cd, m0, [&](auto sc, auto pc, cx<R> v) {
             constexpr int hh = decltype(sc)::value, P8 = decltype(pc)::value;
             constexpr int h2 = hh ^ (SW ? par(P8) : 0);
-            stc(wall + h2 * G::HS + G::W3P * P8 + pm, v);
+            stc(w + h2 * G::HS + G::W3P * P8 + pm, v);
         });
     } else {
         // the row's blocks of 4, 2 and 1 points (slots (W3/8) k), straight to the output layout
@@ -1615,7 +1621,7 @@ __global__ __launch_bounds__(kgeo<LOGN - DEP>::WG) void amqft_kL_rows(cx<R>* __r
     // blocks with at least 8 points: LDS block layout -> the row
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh)
-        for (int pos = tid; pos < W3 - 8; pos += G::WG) row[hh][pos] = ldc(wall + hh * G::HS + pad(pos));
+        for (int pos = m0; pos < W3 - 8; pos += G::T) row[hh][pos] = ldc(w + hh * G::HS + pad(pos));
 }
 
 // N >= 2^18: levels 3..5 of every depth-3 row pair (the F1 levels of its
@@ -1812,6 +1818,7 @@ __global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage
     }
     __syncthreads();
     const int k0 = K + tid;
+    if (k0 >= W3) return;  // N < 2^12: fewer chain threads than the workgroup has
     const cx<R>* w2 = ws2 + sl * N;
     const cx<R>* chn = wsc + sl * 16;
     cx<R> res[16];
@@ -1832,7 +1839,10 @@ __global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage
             const int q = Q >> (3 + t);
             const bool lt = kc < q, gt = kc > q;
             kc = gt ? 2 * q - kc : kc;
-            ic[t] = kc;
+            // harmonic q of a level has no block term (weight 0); its read
+            // goes to index 0 of the block, so that it never touches the
+            // slot past the block's end (unwritten in a global workspace)
+            ic[t] = lt || gt ? kc : 0;
             wc[t] = lt ? R(1) : gt ? R(-1) : R(0);
         }
         int ks = k0;
@@ -1925,11 +1935,13 @@ hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
         hipLaunchKernelGGL((amqft_kL_top<V, S, LOGN>), gw, dim3(256), 0, st, static_cast<const S*>(a.in), ws1, wsc, kt,
                            s0, (long long)a.batch, flags, static_cast<const long long*>(a.offsets));
         if constexpr (DEP == 3) {
-            hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN, 3>), dim3(8, (unsigned)nb), dim3(GR::WG), lds, st, ws1, kt);
+            hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN, 3>), dim3(8 / GR::SPW, (unsigned)nb), dim3(GR::WG), lds, st, ws1,
+                               kt);
         } else {
             constexpr int W6 = N / 128;
             hipLaunchKernelGGL((amqft_kL_rtop<V, R, LOGN>), dim3(W6 / 256, 8, (unsigned)nb), dim3(256), 0, st, ws1, ws2,
                                kt);
+            static_assert(GR::SPW == 1, "depth-6 rows are at least 2^12 points");
             hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN, 6>), dim3(64, (unsigned)nb), dim3(GR::WG), lds, st, ws2, kt);
             hipLaunchKernelGGL((amqft_kL_rback<V, R, LOGN>), dim3(W6 / 256, 16, (unsigned)nb), dim3(256), 0, st,
                                static_cast<const cx<R>*>(ws2), ws1);
@@ -1943,12 +1955,31 @@ hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// 2^11 .. 2^14 (2^13 in FP64) fit one workgroup's LDS; the path runs there
+// only when a plan forces it (tests of its kernels at sizes where every
+// variant is accurate), for FP64 and FP32 storage
 template <int V, typename S>
 hipError_t launch_kL_s(const kl_launch& a, hipStream_t st) {
     if constexpr (std::is_same<S, double2>::value) {
-        if (a.logn == 15) return launch_kL_n<V, S, 15>(a, st);
-        return launch_kL_n<V, S, 16>(a, st);
+        switch (a.logn) {
+        case 11: return launch_kL_n<V, S, 11>(a, st);
+        case 12: return launch_kL_n<V, S, 12>(a, st);
+        case 13: return launch_kL_n<V, S, 13>(a, st);
+        case 14: return launch_kL_n<V, S, 14>(a, st);
+        case 15: return launch_kL_n<V, S, 15>(a, st);
+        default: return launch_kL_n<V, S, 16>(a, st);
+        }
     } else {
+        if constexpr (std::is_same<S, float2>::value) {
+            switch (a.logn) {
+            case 11: return launch_kL_n<V, S, 11>(a, st);
+            case 12: return launch_kL_n<V, S, 12>(a, st);
+            case 13: return launch_kL_n<V, S, 13>(a, st);
+            case 14: return launch_kL_n<V, S, 14>(a, st);
+            default: break;
+            }
+        }
+        if (a.logn < 15) return hipErrorInvalidValue;
         switch (a.logn) {
         case 15: return launch_kL_n<V, S, 15>(a, st);
         case 16: return launch_kL_n<V, S, 16>(a, st);
@@ -2054,16 +2085,23 @@ hipError_t launch_kA_loss(const loss_launch& a, hipStream_t st) {
 
 bool kL_supported(int variant, int logn, int dtype) {
     if (variant != 4 && variant != 8) return false;
-    if (dtype == 0) return logn >= 15 && logn <= 16;
+    if (dtype == 0) return logn >= 14 && logn <= 16;
     return logn >= 15 && logn <= 20;  // FP32 arithmetic: FP32, FP16 and BF16 storage
+}
+
+bool kL_supported_forced(int variant, int logn, int dtype) {
+    if (variant != 4 && variant != 8) return false;
+    if (dtype == 0) return logn >= 11 && logn <= 16;
+    if (dtype == 1) return logn >= 11 && logn <= 20;
+    return kL_supported(variant, logn, dtype);
 }
 
 size_t kL_ws_bytes_per_signal(int logn, int dtype) { return ((size_t)1 << logn) * (dtype == 0 ? 16 : 8); }
 
 hipError_t prime_kL(int variant, int dtype) {
     // the rows kernels depend on the arithmetic type only (float for dtypes 1..3)
-    if (variant == 4) return dtype == 0 ? prime_kL_n<4, double, 15, 16>() : prime_kL_n<4, float, 15, 20>();
-    if (variant == 8) return dtype == 0 ? prime_kL_n<8, double, 15, 16>() : prime_kL_n<8, float, 15, 20>();
+    if (variant == 4) return dtype == 0 ? prime_kL_n<4, double, 11, 16>() : prime_kL_n<4, float, 11, 20>();
+    if (variant == 8) return dtype == 0 ? prime_kL_n<8, double, 11, 16>() : prime_kL_n<8, float, 11, 20>();
     return hipSuccess;
 }
 

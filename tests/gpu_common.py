@@ -8,16 +8,24 @@ stored input):
     variant 4 has 1.1e-5 at N = 2^17), so the bound there is 2x the error of
     that same-precision, same-variant build;
   * variants 5-8 are ill-conditioned by construction (Sec. 7.3: their error
-    "grows far faster"); where their own FP64/FP32 error is above those
-    targets the bound is 20x the error of the oracle's same-variant,
-    same-precision emulation (plus a floor), i.e. the GPU must be as accurate
-    as a faithful implementation of the same variant can be.
+    grows far faster than that of 1-4); where their own FP64/FP32 error is
+    above those targets the bound is 20x the error of the oracle's
+    same-variant, same-precision emulation.
+  * A bound is a pin only while it is at most PIN_CAP: above that (or where
+    the emulation itself is not finite) a case has no pin at all -- a signal
+    of up to 2^20 points with one wrong output value would still pass it.
+    Such cases are reported (error, count of non-finite outputs) and the test
+    is marked xfail with that report; they never count as a pass.
 """
 from __future__ import annotations
+
+import sys
 
 import numpy as np
 
 import oracle
+
+PIN_CAP = 1e-3
 
 
 def rel(a, b):
@@ -33,7 +41,8 @@ def truth(x: np.ndarray, variant: int = 4) -> np.ndarray:
     return oracle.cdft(np.asarray(x, dtype=np.complex128), variant, prec="f64")
 
 
-def bound(variant: int, f64: bool, x: np.ndarray, ref: np.ndarray) -> float:
+def bound(variant: int, f64: bool, x: np.ndarray, ref: np.ndarray):
+    """The pin of this case (a relative L2 bound), or None where none exists."""
     base = 1e-12 if f64 else 1e-5
     n = np.asarray(x).shape[-1]
     if variant <= 4 and (f64 or n <= 1 << 16):
@@ -42,5 +51,32 @@ def bound(variant: int, f64: bool, x: np.ndarray, ref: np.ndarray) -> float:
                       prec="f64" if f64 else "f32")
     e = rel(emu, ref)
     if not np.isfinite(e):
-        return np.inf
-    return max(base, (20.0 if variant > 4 else 2.0) * e)
+        return None
+    b = max(base, (20.0 if variant > 4 else 2.0) * e)
+    return b if b <= PIN_CAP else None
+
+
+def assess(y, ref, variant: int, f64: bool, x, label: str):
+    """Assert y against its pin; for a case without a pin, report the error and
+    the count of non-finite outputs and return that report (the caller marks
+    the test xfail with it).  Returns None for a pinned case that passed."""
+    y = np.asarray(y)
+    b = bound(variant, f64, x, ref)
+    e = rel(y, ref)
+    if b is None:
+        bad = int(np.count_nonzero(~np.isfinite(y.view(np.float32 if y.dtype == np.complex64 else np.float64)
+                                                if np.iscomplexobj(y) else y)))
+        msg = ("%s: no pin (variant %d's own %s emulation error is above %.0e or not finite); "
+               "GPU rel err %.3e, %d non-finite values" % (label, variant, "FP64" if f64 else "FP32", PIN_CAP, e, bad))
+        print("[unpinned]", msg, file=sys.stderr, flush=True)
+        return msg
+    assert e <= b, (label, e, b)
+    return None
+
+
+def xfail_unpinned(reports):
+    """Mark the calling test xfail with the reports of its unpinned cases."""
+    reports = [r for r in reports if r]
+    if reports:
+        import pytest
+        pytest.xfail("; ".join(reports))

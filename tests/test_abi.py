@@ -94,3 +94,16 @@ def test_create_many_validation(lib):
     assert rc == _lib.ERR_INVALID_ARG
     rc = lib.amqft_plan_create_many(ctypes.byref(h), 3, None, O.ctypes.data, 4, 1, 0)
     assert rc == _lib.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kw", [dict(n=1024, flags=8), dict(n=4096, variant=2, flags=8),
+                                dict(n=4096, variant=1, flags=8), dict(n=4096, dtype=2, flags=8),
+                                dict(n=1 << 17, dtype=0, flags=8), dict(n=4096, flags=12)])
+def test_force_large_validation(lib, kw):
+    """The large-N path can be forced only where it exists (variants 4 and 8,
+    N >= 2^11, FP64 / FP32 storage below 2^15) and not with the multi-pass
+    force flag; the refusal happens before any HIP call."""
+    n = kw.pop("n")
+    rc, h = _create(lib, n, **kw)
+    assert rc == _lib.ERR_UNSUPPORTED
+    assert not h.value

@@ -7,7 +7,7 @@ import sys
 import numpy as np
 import pytest
 
-from gpu_common import bound, rel, truth
+from gpu_common import assess, bound, rel, truth, xfail_unpinned
 from paper_1404_1810_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -36,37 +36,33 @@ def _run(x_np, variant, dtype, flags=0, adjoint=False):
     return y.cpu().numpy()
 
 
-SIZES_F32 = [1, 2, 4, 8, 16, 32, 64, 128, 256, 1024, 4096, 16384]
-SIZES_F64 = [1, 2, 4, 8, 16, 64, 256, 1024, 8192]
+SIZES_F32 = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384]
+SIZES_F64 = [1, 2, 4, 8, 16, 64, 256, 512, 1024, 2048, 4096, 8192]
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("n", SIZES_F32)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_parity_fp32(variant):
-    for n in SIZES_F32:
-        batch = 3 if n >= 4096 else 37  # ragged: not a multiple of signals-per-workgroup
-        _say("fp32 parity variant", variant, "n", n, "batch", batch)
-        x = inputs.complex_normal(1000 + n, batch, n).astype(np.complex64)
-        ref = truth(x, 2 if variant in (2, 3, 6, 7) else 4)
-        y = _run(x, variant, "c64")
-        assert y.dtype == np.complex64
-        b = bound(variant, False, x, ref)
-        e = rel(y, ref)
-        assert e <= b, (variant, n, e, b)
+def test_parity_fp32(variant, n):
+    batch = 3 if n >= 4096 else 37  # ragged: not a multiple of signals-per-workgroup
+    _say("fp32 parity variant", variant, "n", n, "batch", batch)
+    x = inputs.complex_normal(1000 + n, batch, n).astype(np.complex64)
+    ref = truth(x, 2 if variant in (2, 3, 6, 7) else 4)
+    y = _run(x, variant, "c64")
+    assert y.dtype == np.complex64
+    xfail_unpinned([assess(y, ref, variant, False, x, "fp32 n=%d" % n)])
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("n", SIZES_F64)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_parity_fp64(variant):
-    for n in SIZES_F64:
-        batch = 2 if n >= 4096 else 19
-        _say("fp64 parity variant", variant, "n", n, "batch", batch)
-        x = inputs.complex_uniform(2000 + n, batch, n)
-        ref = truth(x, 4)
-        y = _run(x, variant, "c128")
-        b = bound(variant, True, x, ref)
-        e = rel(y, ref)
-        assert e <= b, (variant, n, e, b)
+def test_parity_fp64(variant, n):
+    batch = 2 if n >= 4096 else 19
+    _say("fp64 parity variant", variant, "n", n, "batch", batch)
+    x = inputs.complex_uniform(2000 + n, batch, n)
+    ref = truth(x, 4)
+    y = _run(x, variant, "c128")
+    xfail_unpinned([assess(y, ref, variant, True, x, "fp64 n=%d" % n)])
 
 
 @pytest.mark.gpu
@@ -77,7 +73,8 @@ def test_adjoint_parity(variant):
     g = inputs.complex_normal(77, batch, n)
     ref = np.conj(truth(np.conj(g), 4))  # F^H g
     y = _run(g, variant, "c128", adjoint=True)
-    assert rel(y, ref) <= bound(variant, True, np.conj(g), np.conj(ref))
+    b = bound(variant, True, np.conj(g), np.conj(ref))
+    assert b is not None and rel(y, ref) <= b
 
 
 @pytest.mark.gpu
@@ -150,104 +147,192 @@ def test_fp64_repeated_launches_identical(n):
     assert e <= 1e-12, (n, e)
 
 
+MP_FORCED = (("c64", 32), ("c64", 128), ("c64", 1024), ("c64", 4096), ("c128", 256), ("c128", 1024), ("c128", 2048))
+
+
 @pytest.mark.gpu
+@pytest.mark.parametrize("dtype,n", MP_FORCED)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_multipass_forced_small(variant):
+def test_multipass_forced_small(variant, dtype, n):
     """The multi-pass path (global levels + LDS sub-blocks + tail) forced at
-    small N, where it uses 4..32-point sub-blocks and three global levels."""
-    for dtype, n in (("c64", 32), ("c64", 128), ("c64", 1024), ("c128", 256), ("c64", 4096)):
-        batch = 3
-        _say("forced multipass", dtype, "variant", variant, "n", n)
-        x = inputs.complex_normal(3000 + n, batch, n)
-        if dtype == "c64":
-            x = x.astype(np.complex64)
-        ref = truth(x, 4)
-        y = _run(x, variant, dtype, flags=4)
-        e = rel(y, ref)
-        assert e <= bound(variant, dtype == "c128", x, ref), (dtype, n, e)
+    small N, where it uses 4..64-point sub-blocks and several global levels.
+    Its FP64 cases up to 2^11 pin every kernel of the engine for all eight
+    variants (the same kernels serve N = 2^15 .. 2^24)."""
+    batch = 3
+    _say("forced multipass", dtype, "variant", variant, "n", n)
+    x = inputs.complex_normal(3000 + n, batch, n)
+    if dtype == "c64":
+        x = x.astype(np.complex64)
+    ref = truth(x, 4)
+    y = _run(x, variant, dtype, flags=4)
+    xfail_unpinned([assess(y, ref, variant, dtype == "c128", x, "forced multipass %s n=%d" % (dtype, n))])
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("dtype,n", (("c64", 1 << 15), ("c64", 1 << 16), ("c128", 1 << 14)))
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_multipass_large(variant):
+def test_multipass_large(variant, dtype, n):
     """Signals above the LDS capacity: 2^15 and 2^16 (FP32), 2^14 (FP64)."""
-    for dtype, n, batch in (("c64", 1 << 15, 2), ("c64", 1 << 16, 2), ("c128", 1 << 14, 2)):
-        _say("multipass", dtype, "variant", variant, "n", n)
-        x = inputs.complex_normal(4000 + n, batch, n)
-        if dtype == "c64":
-            x = x.astype(np.complex64)
-        ref = truth(x, 4)
-        y = _run(x, variant, dtype)
-        e = rel(y, ref)
-        b = bound(variant, dtype == "c128", x, ref)
-        if np.isfinite(b):
-            assert e <= b, (dtype, n, e, b)
+    batch = 2
+    _say("multipass", dtype, "variant", variant, "n", n)
+    x = inputs.complex_normal(4000 + n, batch, n)
+    if dtype == "c64":
+        x = x.astype(np.complex64)
+    ref = truth(x, 4)
+    y = _run(x, variant, dtype)
+    xfail_unpinned([assess(y, ref, variant, dtype == "c128", x, "%s n=%d" % (dtype, n))])
+
+
+def _large_case(api, _lib, variant, dtype, n, batch, flags_extra, want_chunk=None, adjoint=True):
+    x_np = inputs.complex_normal(5000 + n, batch, n)
+    if dtype == "c64":
+        x_np = x_np.astype(np.complex64)
+    f64 = dtype == "c128"
+    ref = truth(x_np, 4)
+    aref = np.conj(truth(np.conj(x_np), 4))
+    x = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
+    reports = []
+    for flags in (0, _lib.FLAG_ONTHEFLY_CONSTANTS):
+        plan = api.Plan(n, batch, variant, _lib.C128 if f64 else _lib.C64, flags | flags_extra)
+        d = plan.describe()
+        assert "amqft_kL" in d, d
+        if want_chunk is not None:
+            assert ("chunk=%d" % want_chunk) in d, d
+        y = plan.exec(x)
+        torch.cuda.synchronize()
+        reports.append(assess(y.cpu().numpy(), ref, variant, f64, x_np, "%s n=%d flags=%d" % (dtype, n, flags)))
+        if flags == 0 and adjoint:
+            g = x.clone()
+            plan.exec(g, out=g, adjoint=True)  # in place
+            torch.cuda.synchronize()
+            reports.append(assess(np.conj(g.cpu().numpy()), np.conj(aref), variant, f64, np.conj(x_np),
+                                  "%s n=%d adjoint in place" % (dtype, n)))
+        plan.close()
+    return reports
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("dtype,n,batch,chunk", (("c64", 1 << 15, 5, 4), ("c64", 1 << 17, 3, 1),
+                                                 ("c128", 1 << 14, 5, 4), ("c128", 1 << 15, 3, 2),
+                                                 ("c128", 1 << 16, 2, 1)))
 @pytest.mark.parametrize("variant", [4, 8])
-def test_large_path(variant, monkeypatch):
+def test_large_path(variant, dtype, n, batch, chunk, monkeypatch):
     """The four-kernel path for N above one workgroup's LDS (variants 4 and 8:
-    2^15 .. 2^17 FP32, 2^15 .. 2^16 FP64), its workspaces cut to 1 MiB so that
+    2^15 .. 2^17 FP32, 2^14 .. 2^16 FP64), its workspaces cut to 1 MiB so that
     every batch runs in several chunks with a ragged last one; forward with the
-    table and with on-the-fly constants, adjoint, in place."""
+    table and with on-the-fly constants, adjoint, in place.  Variant 8 has no
+    pin at these sizes (its own FP64 error is above 1e-3 from 2^13); its
+    kernels are pinned by test_large_path_forced."""
     api = _api()
     from paper_1404_1810_amd import _lib
     monkeypatch.setenv("AMQFT_LARGE_WS_MB", "1")
-    cases = (("c64", 1 << 15, 5, 4), ("c64", 1 << 17, 3, 1), ("c128", 1 << 15, 3, 2), ("c128", 1 << 16, 2, 1))
-    for dtype, n, batch, chunk in cases:
-        _say("large path", dtype, "variant", variant, "n", n, "batch", batch)
-        x_np = inputs.complex_normal(5000 + n, batch, n)
-        if dtype == "c64":
-            x_np = x_np.astype(np.complex64)
-        ref = truth(x_np, 4)
-        b = bound(variant, dtype == "c128", x_np, ref)
-        tdt = torch.complex128 if dtype == "c128" else torch.complex64
-        x = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
-        for flags in (0, _lib.FLAG_ONTHEFLY_CONSTANTS):
-            plan = api.Plan(n, batch, variant, _lib.C128 if dtype == "c128" else _lib.C64, flags)
-            d = plan.describe()
-            assert "amqft_kL" in d and ("chunk=%d" % chunk) in d, d
-            y = plan.exec(x)
-            torch.cuda.synchronize()
-            e = rel(y.cpu().numpy(), ref)
-            assert e <= b, (dtype, n, flags, e, b)
-            if flags == 0:
-                g = x.clone()
-                plan.exec(g, out=g, adjoint=True)  # in place
-                torch.cuda.synchronize()
-                ea = rel(g.cpu().numpy(), np.conj(truth(np.conj(x_np), 4)))
-                assert ea <= b, (dtype, n, "adjoint", ea, b)
-            plan.close()
-        assert x.dtype == tdt
+    _say("large path", dtype, "variant", variant, "n", n, "batch", batch)
+    xfail_unpinned(_large_case(api, _lib, variant, dtype, n, batch, 0, want_chunk=chunk))
+
+
+LARGE_FORCED = (("c128", 1 << 11, 5), ("c128", 1 << 12, 3), ("c128", 1 << 13, 2), ("c64", 1 << 11, 5),
+                ("c64", 1 << 12, 3), ("c64", 1 << 13, 2), ("c64", 1 << 14, 2))
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("dtype,n,batch", LARGE_FORCED)
 @pytest.mark.parametrize("variant", [4, 8])
-def test_large_path_deep(variant):
-    """N = 2^18 and 2^20 (FP32) on the six-kernel path: depth-3 rows split once
-    more into depth-6 rows; table and device-generated constants, adjoint."""
+def test_large_path_forced(variant, dtype, n, batch, monkeypatch):
+    """The same four kernels (top, rows, back, bchain) forced at N = 2^11 ..
+    2^14, where the rows are 2^8 .. 2^11-point transforms that share a
+    workgroup.  At FP64 2^11 and 2^12 every kernel of variant 8 is pinned at
+    20x its own FP64 error (<= 5e-5); forward with table and on-the-fly
+    constants, adjoint in place, chunks of 1 MiB of workspace."""
     api = _api()
     from paper_1404_1810_amd import _lib
-    for n, batch in ((1 << 18, 2), (1 << 20, 1)):
-        _say("deep large path c64 variant", variant, "n", n, "batch", batch)
-        x_np = inputs.complex_normal(6000 + n, batch, n).astype(np.complex64)
-        ref = truth(x_np, 4)
-        b = bound(variant, False, x_np, ref)
-        x = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
-        for flags in (0, _lib.FLAG_ONTHEFLY_CONSTANTS):
-            plan = api.Plan(n, batch, variant, _lib.C64, flags)
-            assert "rtop" in plan.describe(), plan.describe()
-            y = plan.exec(x)
+    monkeypatch.setenv("AMQFT_LARGE_WS_MB", "1")
+    _say("forced large path", dtype, "variant", variant, "n", n, "batch", batch)
+    xfail_unpinned(_large_case(api, _lib, variant, dtype, n, batch, _lib.FLAG_FORCE_LARGE))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [1 << 18, 1 << 20])
+@pytest.mark.parametrize("variant", [4, 8])
+def test_large_path_deep(variant, n):
+    """N = 2^18 and 2^20 (FP32) on the six-kernel path: depth-3 rows split once
+    more into depth-6 rows; table and device-generated constants, adjoint.
+    The depth-6 kernels (rtop, rback) exist only from 2^18, where variant 8
+    has no pin: its cases are reported, not asserted."""
+    api = _api()
+    from paper_1404_1810_amd import _lib
+    batch = 2 if n == 1 << 18 else 1
+    _say("deep large path c64 variant", variant, "n", n, "batch", batch)
+    x_np = inputs.complex_normal(6000 + n, batch, n).astype(np.complex64)
+    ref = truth(x_np, 4)
+    x = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
+    reports = []
+    for flags in (0, _lib.FLAG_ONTHEFLY_CONSTANTS):
+        plan = api.Plan(n, batch, variant, _lib.C64, flags)
+        assert "rtop" in plan.describe(), plan.describe()
+        y = plan.exec(x)
+        torch.cuda.synchronize()
+        reports.append(assess(y.cpu().numpy(), ref, variant, False, x_np, "n=%d flags=%d" % (n, flags)))
+        if flags == 0 and n == 1 << 18:
+            g = plan.exec(x, adjoint=True)
             torch.cuda.synchronize()
-            e = rel(y.cpu().numpy(), ref)
-            _say("  flags", flags, "rel err", e, "bound", b)
-            # (variant 8 overflows FP32 at 2^20 in the oracle's FP32 build too:
-            # no finite bound, the result is reported only)
-            assert not np.isfinite(b) or e <= b, (n, flags, e, b)
-            if flags == 0 and n == 1 << 18 and np.isfinite(b):
-                g = plan.exec(x, adjoint=True)
-                torch.cuda.synchronize()
-                ea = rel(g.cpu().numpy(), np.conj(truth(np.conj(x_np), 4)))
-                assert ea <= b, (n, "adjoint", ea, b)
-            plan.close()
+            reports.append(assess(np.conj(g.cpu().numpy()), np.conj(np.conj(truth(np.conj(x_np), 4))), variant,
+                                  False, np.conj(x_np), "n=%d adjoint" % n))
+        plan.close()
+    xfail_unpinned(reports)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_plan_constants_device_table(variant, dtype):
+    """amqft_plan_constants returns what the kernels read: the host table
+    (long double, rounded once) without the on-the-fly flag, the device FP64
+    table with it.  The two agree bit for bit in FP32 except where the FP64
+    value lies within 2^-40 (relative) of a halfway point between two floats
+    (double rounding); in FP64 within 4 ulp (the device's cospi / sinpi and the
+    reciprocal round separately)."""
+    api = _api()
+    from paper_1404_1810_amd import _lib
+    for n in (1 << 10, 1 << 16):
+        _say("constants variant", variant, "dtype", dtype, "n", n)
+        host = api.Plan(n, 1, variant, dtype, 0)
+        dev = api.Plan(n, 1, variant, dtype, _lib.FLAG_ONTHEFLY_CONSTANTS)
+        a, b = host.constants(), dev.constants()
+        host.close()
+        dev.close()
+        assert a.shape == b.shape == (n // 4,)
+        assert a[0] == 0 and b[0] == 0
+        fam = {1: 0, 2: 1, 3: 0, 4: 1, 5: 2, 6: 3, 7: 2, 8: 3}[variant]
+        p = np.arange(1, n // 4, dtype=np.longdouble)
+        ang = 2 * np.pi * p / np.longdouble(n)  # numpy's pi: exact to double, enough for the tie test
+        exact = {0: 2 * np.cos(ang), 1: 1 / (2 * np.cos(ang)), 2: 2 * np.sin(ang), 3: 1 / (2 * np.sin(ang))}[fam]
+        if dtype == 1:
+            diff = np.nonzero(a[1:] != b[1:])[0]
+            for i in diff:
+                lo, hi = sorted((np.float32(a[1 + i]), np.float32(b[1 + i])))
+                assert np.nextafter(lo, np.float32(np.inf)) == hi, (variant, n, i)
+                mid = (np.longdouble(lo) + np.longdouble(hi)) / 2
+                assert abs(exact[i] - mid) <= abs(mid) * 2.0 ** -40, (variant, n, i, a[1 + i], b[1 + i])
+            assert len(diff) <= max(2, n // 4 // 1000), (variant, n, len(diff))
+        else:
+            ulp = np.spacing(np.abs(a[1:]))
+            assert np.all(np.abs(a[1:] - b[1:]) <= 4 * ulp), (variant, n)
+
+
+@pytest.mark.gpu
+def test_alloc_failure_status(monkeypatch):
+    """A plan whose workspace cannot be allocated returns AMQFT_ERR_ALLOC (and
+    no plan); nothing is launched.  2^21 signals of 2^15 points with one chunk
+    spanning all of them: 512 GiB per workspace buffer."""
+    from paper_1404_1810_amd import _lib
+    import ctypes
+    lib = _lib.load()
+    monkeypatch.setenv("AMQFT_LARGE_WS_MB", str(1 << 20))
+    h = ctypes.c_void_p(1)
+    _say("allocation failure")
+    st = lib.amqft_plan_create(ctypes.byref(h), 1 << 15, 1 << 21, 4, _lib.C64, 0)
+    assert st == _lib.ERR_ALLOC, st
+    assert not h.value
+    torch.cuda.synchronize()
+    x = torch.ones(4, 64, dtype=torch.complex64, device="cuda")  # the device still works
+    assert torch.allclose(_api().fft(x, 4)[:, 0], torch.full((4,), 64, dtype=torch.complex64, device="cuda"))

@@ -6,7 +6,7 @@ import sys
 import numpy as np
 import pytest
 
-from gpu_common import bound, rel, truth
+from gpu_common import assess, rel, truth, xfail_unpinned
 from paper_1404_1810_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -37,12 +37,14 @@ def test_uneven_against_oracle(variant):
     y = torch.full_like(x, complex(7.0, 7.0))
     plan.exec(x, out=y)
     got = y.cpu().numpy()
+    reports = []
     for i, (n, o) in enumerate(zip(lengths, offsets[:-1])):
         seg = buf[o:o + n]
         ref = truth(seg[None, :], 4)[0]
-        e = rel(got[o:o + n], ref)
-        assert e <= bound(variant, False, seg[None, :], ref[None, :]), (i, n, e)
         assert np.all(got[o + n:offsets[i + 1]] == np.complex64(7 + 7j))  # gaps untouched
+        reports.append(assess(got[o:o + n][None, :], ref[None, :], variant, False, seg[None, :],
+                              "signal %d n=%d" % (i, n)))
+    xfail_unpinned(reports)
 
 
 @pytest.mark.gpu
@@ -147,6 +149,6 @@ def test_uneven_long_classes_only(dtype):
             ref = truth(src[None, :], 4)[0]
             if adjoint:
                 ref = np.conj(ref)
-            e = rel(got[o:o + n], ref)
-            assert e <= bound(4, f64, seg[None, :], ref[None, :]), (i, n, adjoint, e)
+            assert assess(got[o:o + n][None, :], ref[None, :], 4, f64, src[None, :],
+                          "signal %d n=%d adjoint=%s" % (i, n, adjoint)) is None
             assert np.all(got[o + n:offsets[i + 1]] == 7 + 7j)
