@@ -177,6 +177,32 @@ amqft_status amqft_plan_workspace_size(amqft_plan plan, size_t *bytes);
 amqft_status amqft_plan_constants(amqft_plan plan, int64_t n, double *table_host,
                                   int64_t entries);
 
+/* Bytes of the device array each GPU holds for amqft_exec_noalloc. */
+#define AMQFT_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): X = F x (adjoint = 0) or
+ * y = F^H g (adjoint = 1) of `batch` signals of length n (stride n) on the
+ * current device, asynchronously on `stream`, with no plan and no
+ * allocation of any kind.  Same kernels, same results (bit for bit) as a
+ * plan made by amqft_plan_create with AMQFT_FLAG_ONTHEFLY_CONSTANTS:
+ * constants are always generated on the device in FP64.  The paths above
+ * one workgroup's LDS keep their workspace and constant table in a
+ * file-scope device array of AMQFT_NOALLOC_SCRATCH_BYTES per GPU (held
+ * until the process ends); signals run in chunks that fit it, and a length
+ * whose single signal does not fit (n above 2^21 for FP32 storage, 2^20 for
+ * FP64) returns AMQFT_ERR_UNSUPPORTED before any HIP call.  Every call on
+ * one GPU uses the same array and leaves its contents behind (nothing in it
+ * needs to start at zero): calls that overlap on one GPU (two streams, or
+ * two host threads) race and must be serialised by the caller.  The first
+ * call on a device resolves the array's address and sets kernel attributes
+ * (no allocation).  in_dev == out_dev is allowed.  Errors as for
+ * amqft_plan_create / amqft_exec. */
+amqft_status amqft_exec_noalloc(int64_t n, int64_t batch, amqft_variant variant,
+                                amqft_dtype dtype, int adjoint,
+                                const void *in_dev, void *out_dev,
+                                void *stream);
+
 /* Static description of a status code. */
 const char *amqft_status_string(amqft_status status);
 

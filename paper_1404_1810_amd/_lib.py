@@ -18,6 +18,7 @@ FLAG_ONTHEFLY_CONSTANTS = 1
 FLAG_NO_AUTOTUNE = 2
 FLAG_FORCE_MULTIPASS = 4
 FLAG_FORCE_LARGE = 8
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 #: every function the header declares, with its ctypes signature
 SIGNATURES = {
@@ -35,6 +36,8 @@ SIGNATURES = {
     "amqft_plan_describe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
     "amqft_plan_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "amqft_plan_constants": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64]),
+    "amqft_exec_noalloc": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "amqft_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "amqft_last_hip_error": (ctypes.c_char_p, []),
     "amqft_version": (ctypes.c_char_p, []),

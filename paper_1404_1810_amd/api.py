@@ -277,3 +277,22 @@ def exec_graph(plan: Plan, x: torch.Tensor, out: torch.Tensor, adjoint: bool = F
                                             ctypes.c_void_p(out.data_ptr()), 1 if adjoint else 0,
                                             _stream_handle(x.device)), "amqft_exec_graph")
     return out
+
+
+def exec_noalloc(x: torch.Tensor, variant: int = 4, adjoint: bool = False,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """amqft_exec_noalloc: the transform along the last axis with no plan and no
+    allocation inside the library (its workspace is a fixed device array per
+    GPU; calls that overlap on one GPU race).  `out` may be given so that the
+    call allocates nothing at all."""
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("input must be a contiguous GPU tensor (the AM-QFT path has no CPU fallback)")
+    dt, n, batch = _storage(x)
+    y = torch.empty_like(x) if out is None else out
+    if y.device != x.device or y.dtype != x.dtype or y.shape != x.shape or not y.is_contiguous():
+        raise ValueError("output must be a contiguous tensor of the input's shape, dtype and device")
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.load().amqft_exec_noalloc(int(n), int(batch), int(variant), int(dt), 1 if adjoint else 0,
+                                                  ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                                  _stream_handle(x.device)), "amqft_exec_noalloc")
+    return y

@@ -477,6 +477,8 @@ amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int varian
 
 }  // namespace
 
+int amqft::record_hip_failure(hipError_t e) { return (int)hip_fail(e); }
+
 extern "C" {
 
 const char* amqft_version(void) { return "amqft 0.2.0 (gfx950)"; }

@@ -137,6 +137,10 @@ hipError_t prime_lds(int variant, int dtype);
 hipError_t fill_table_device(void* ktab, int variant, int dtype, int logn, hipStream_t stream);
 hipError_t prime_multipass(int variant, int dtype);
 
+// Record a failed HIP call as the calling thread's last HIP error (read by
+// amqft_last_hip_error) and return the amqft_status it maps to.
+int record_hip_failure(hipError_t e);
+
 // Bytes of dynamic LDS and threads per workgroup the LDS engine uses.
 void lds_shape(int logn, int dtype, int* threads, int* signals_per_wg, size_t* lds_bytes);
 

@@ -107,3 +107,18 @@ def test_force_large_validation(lib, kw):
     rc, h = _create(lib, n, **kw)
     assert rc == _lib.ERR_UNSUPPORTED
     assert not h.value
+
+
+def test_noalloc_validation(lib):
+    """amqft_exec_noalloc rejects bad arguments, and lengths whose single
+    signal does not fit its fixed scratch array, before any HIP call."""
+    f = lib.amqft_exec_noalloc
+    assert f(1 << 22, 1, 4, 1, 0, None, None, None) == _lib.ERR_UNSUPPORTED  # FP32: 3 x 32 MiB workspace
+    assert f(1 << 21, 1, 2, 0, 0, None, None, None) == _lib.ERR_UNSUPPORTED  # FP64: 3 x 32 MiB
+    assert f(1 << 25, 1, 4, 1, 0, None, None, None) == _lib.ERR_UNSUPPORTED
+    assert f(3, 1, 4, 1, 0, None, None, None) == _lib.ERR_NOT_POW2
+    assert f(64, 1, 9, 1, 0, None, None, None) == _lib.ERR_INVALID_ARG
+    assert f(64, -1, 4, 1, 0, None, None, None) == _lib.ERR_INVALID_ARG
+    assert f(64, 1, 4, 4, 0, None, None, None) == _lib.ERR_INVALID_ARG
+    assert f(64, 0, 4, 1, 0, None, None, None) == _lib.OK  # empty batch: nothing to do
+    assert f(64, 2, 4, 1, 0, None, None, None) == _lib.ERR_INVALID_ARG  # null buffers
