@@ -105,6 +105,36 @@ amqft_status amqft_plan_create(amqft_plan *out, int64_t n, int64_t batch,
                                amqft_variant variant, amqft_dtype dtype,
                                unsigned flags);
 
+/* Real transforms of the same recursion (Sec. 3.1, Sec. 7.4: the CDFT is
+ * D_c / D_r, one DCT-0, one DST-0 and the combine of eqs. qft_17-21; these
+ * are the parts of it). */
+typedef enum {
+    /* R(k) = sum_n r(n) exp(-i 2 pi n k / n), k = 0 .. n/2, of a real signal
+     * (eqs. qft_22 - qft_25: D_c / D_r, dct[n] and dst[n]): in n reals, out
+     * n/2 + 1 interleaved complex values per signal. */
+    AMQFT_RDFT = 0,
+    /* The dct[n] function: S(k) = sum_{m=0}^{n/2} s(m) cos(2 pi m k / n),
+     * k = 0 .. n/2: in and out n/2 + 1 reals per signal (eq. qft_0B). */
+    AMQFT_DCT0 = 1,
+    /* The dst[n] function: S(k) = sum_{m=1}^{n/2-1} s(m) sin(2 pi m k / n),
+     * k = 1 .. n/2 - 1: in and out n/2 - 1 reals per signal (eq. qft_0C). */
+    AMQFT_DST0 = 2
+} amqft_real_kind;
+
+/* Plan for `batch` real signals of one real transform of length n (the
+ * periodization, a power of two, 4 <= n <= 2^14 for AMQFT_C64 = FP32 reals
+ * and 2^13 for AMQFT_C128 = FP64 reals; AMQFT_ERR_UNSUPPORTED for other sizes
+ * and storage types, and for the force flags).  Signals are stored back to
+ * back with the strides given above, for input and output alike.  Executed by
+ * amqft_exec; amqft_exec_adjoint gives the same result as amqft_exec for
+ * AMQFT_DCT0 and AMQFT_DST0 (real symmetric matrices) and
+ * AMQFT_ERR_UNSUPPORTED for AMQFT_RDFT.  Two real signals share one complex
+ * lane of the recursion (its coefficients are real), so a batch costs about
+ * half the complex transforms of its size. */
+amqft_status amqft_plan_create_real(amqft_plan *out, int64_t n, int64_t batch,
+                                    amqft_real_kind kind, amqft_variant variant,
+                                    amqft_dtype dtype, unsigned flags);
+
 /* Plan for `count` signals of (possibly different) power-of-two lengths in
  * one buffer: signal i has lengths_host[i] points and starts at complex
  * element offsets_host[i]; offsets_host has count+1 entries, is

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libamqft.so")
 # enums of include/amqft.h
 C128, C64, C32H, C32B = 0, 1, 2, 3
 OK, ERR_INVALID_ARG, ERR_NOT_POW2, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP = range(6)
+RDFT, DCT0, DST0 = 0, 1, 2
 FLAG_ONTHEFLY_CONSTANTS = 1
 FLAG_NO_AUTOTUNE = 2
 FLAG_FORCE_MULTIPASS = 4
@@ -26,6 +27,8 @@ SIGNATURES = {
                                          ctypes.c_int, ctypes.c_int, ctypes.c_uint]),
     "amqft_plan_create_many": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_uint]),
+    "amqft_plan_create_real": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int64, ctypes.c_int64,
+                                              ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint]),
     "amqft_exec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "amqft_exec_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "amqft_power_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,

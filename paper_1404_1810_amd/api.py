@@ -296,3 +296,93 @@ def exec_noalloc(x: torch.Tensor, variant: int = 4, adjoint: bool = False,
                                                   ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                                   _stream_handle(x.device)), "amqft_exec_noalloc")
     return y
+
+
+_REAL_KINDS = {"rdft": _lib.RDFT, "dct0": _lib.DCT0, "dst0": _lib.DST0}
+_REAL_DTYPES = {torch.float64: _lib.C128, torch.float32: _lib.C64}
+
+
+class RealPlan:
+    """amqft_plan_create_real: RDFT, DCT-0 or DST-0 of real signals of
+    periodization n, batch signals back to back (see include/amqft.h for the
+    strides).  Two real signals share one complex lane of the recursion."""
+
+    def __init__(self, n: int, batch: int, kind: str = "rdft", variant: int = 4, dtype: int = _lib.C64,
+                 flags: int = 0):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(lib.amqft_plan_create_real(ctypes.byref(h), int(n), int(batch), _REAL_KINDS[kind], int(variant),
+                                              int(dtype), int(flags)), "amqft_plan_create_real")
+        self._h = h
+        self.n, self.batch, self.kind, self.variant, self.dtype = int(n), int(batch), kind, int(variant), int(dtype)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.load().amqft_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            if self._h is not None and self._h.value and torch.cuda.is_available():
+                torch.cuda.synchronize()
+            self.close()
+        except Exception:
+            pass
+
+    def describe(self) -> str:
+        return _describe(self._h)
+
+    @property
+    def in_len(self) -> int:
+        return {"rdft": self.n, "dct0": self.n // 2 + 1, "dst0": self.n // 2 - 1}[self.kind]
+
+    def exec(self, x: torch.Tensor, out: torch.Tensor | None = None, adjoint: bool = False) -> torch.Tensor:
+        rdt = torch.float64 if self.dtype == _lib.C128 else torch.float32
+        if not x.is_cuda or not x.is_contiguous() or x.dtype != rdt:
+            raise ValueError("input must be a contiguous GPU tensor of dtype %s" % rdt)
+        if x.numel() != self.batch * self.in_len or (x.dim() and x.shape[-1] != self.in_len):
+            raise ValueError("input does not match the plan (batch %d x %d)" % (self.batch, self.in_len))
+        if self.kind == "rdft":
+            shape = tuple(x.shape[:-1]) + (self.n // 2 + 1,)
+            y = torch.empty(shape, dtype=torch.complex128 if rdt == torch.float64 else torch.complex64,
+                            device=x.device) if out is None else out
+            want = self.batch * (self.n // 2 + 1)
+        else:
+            y = torch.empty_like(x) if out is None else out
+            want = self.batch * self.in_len
+        if not y.is_cuda or not y.is_contiguous() or y.device != x.device or y.numel() != want:
+            raise ValueError("output does not match the plan")
+        fn = _lib.load().amqft_exec_adjoint if adjoint else _lib.load().amqft_exec
+        _lib.check(fn(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                      _stream_handle(x.device)), "amqft_exec")
+        return y
+
+
+def _real(kind: str, x: torch.Tensor, n: int, variant: int) -> torch.Tensor:
+    x = x.contiguous()
+    if x.dtype not in _REAL_DTYPES:
+        raise TypeError("real transforms take float32 or float64 tensors")
+    batch = x.numel() // x.shape[-1] if x.shape[-1] else 0
+    dev = x.device.index if x.device.index is not None else torch.cuda.current_device()
+    key = ("real", kind, n, batch, variant, _REAL_DTYPES[x.dtype], dev)
+    p = _plan_cache.get(key)
+    if p is None:
+        with torch.cuda.device(dev):
+            p = RealPlan(n, batch, kind, variant, _REAL_DTYPES[x.dtype])
+        _plan_cache[key] = p
+    return p.exec(x)
+
+
+def rdft(x: torch.Tensor, variant: int = 4) -> torch.Tensor:
+    """R(k), k = 0..n/2, of real signals along the last axis (n = x.shape[-1])."""
+    return _real("rdft", x, x.shape[-1], variant)
+
+
+def dct0(s: torch.Tensor, variant: int = 4) -> torch.Tensor:
+    """DCT-0 (eq. qft_0B) of s(0..n/2) along the last axis (n = 2 (len - 1))."""
+    return _real("dct0", s, 2 * (s.shape[-1] - 1), variant)
+
+
+def dst0(s: torch.Tensor, variant: int = 4) -> torch.Tensor:
+    """DST-0 (eq. qft_0C) of s(1..n/2-1) along the last axis (n = 2 (len + 1))."""
+    return _real("dst0", s, 2 * (s.shape[-1] + 1), variant)

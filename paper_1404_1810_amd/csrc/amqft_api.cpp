@@ -47,6 +47,7 @@ struct amqft_plan_s {
     int64_t n = 0;
     int logn = 0;
     int64_t batch = 0;
+    int real_kind = -1;  // amqft_real_kind of a real-transform plan, -1 for the CDFT
     // constant table for length 2^ktab_log2n, working precision, on device
     void* ktab = nullptr;
     int ktab_log2n = 2;
@@ -204,6 +205,23 @@ void tune_put(const std::string& key, int v) {
 
 amqft_status exec_single(amqft_plan p, const void* in, void* out, hipStream_t stream, bool adjoint) {
     if (p->batch == 0) return AMQFT_OK;
+    if (p->real_kind >= 0) {
+        // the DCT-0 and DST-0 matrices are symmetric and real: their adjoint is the transform itself
+        if (adjoint && p->real_kind == AMQFT_RDFT) return AMQFT_ERR_UNSUPPORTED;
+        real_launch r{};
+        r.variant = p->variant;
+        r.dtype = p->dtype;
+        r.logn = p->logn;
+        r.kind = p->real_kind;
+        r.nreal = p->batch;
+        r.in = in;
+        r.out = out;
+        r.ktab = p->ktab;
+        r.ktab_log2n = p->ktab_log2n;
+        r.onthefly = (p->flags & AMQFT_FLAG_ONTHEFLY_CONSTANTS) != 0;
+        hipError_t e = launch_real(r, stream);
+        return e == hipSuccess ? AMQFT_OK : hip_fail(e);
+    }
     if (p->large) {
         kl_launch k{};
         k.variant = p->variant;
@@ -515,6 +533,37 @@ amqft_status amqft_plan_create(amqft_plan* out, int64_t n, int64_t batch, amqft_
     return create_single(out, n, batch, (int)variant, (int)dtype, flags);
 }
 
+amqft_status amqft_plan_create_real(amqft_plan* out, int64_t n, int64_t batch, amqft_real_kind kind,
+                                    amqft_variant variant, amqft_dtype dtype, unsigned flags) {
+    if (!out) return AMQFT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!valid_variant((int)variant) || !valid_dtype((int)dtype) || batch < 0) return AMQFT_ERR_INVALID_ARG;
+    if ((int)kind < AMQFT_RDFT || (int)kind > AMQFT_DST0) return AMQFT_ERR_INVALID_ARG;
+    if (flags & ~kAllFlags) return AMQFT_ERR_INVALID_ARG;
+    const int logn = log2_exact(n);
+    if (logn < 0) return AMQFT_ERR_NOT_POW2;
+    if (flags & kForceFlags) return AMQFT_ERR_UNSUPPORTED;
+    if (dtype != AMQFT_C128 && dtype != AMQFT_C64) return AMQFT_ERR_UNSUPPORTED;
+    if (logn < 2 || logn > max_lds_log2((int)dtype)) return AMQFT_ERR_UNSUPPORTED;
+    if (batch > (int64_t(1) << 40)) return AMQFT_ERR_UNSUPPORTED;
+    amqft_plan_s* p = new (std::nothrow) amqft_plan_s();
+    if (!p) return AMQFT_ERR_ALLOC;
+    p->variant = (int)variant;
+    p->dtype = (int)dtype;
+    p->flags = flags;
+    p->n = n;
+    p->logn = logn;
+    p->batch = batch;
+    p->real_kind = (int)kind;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { delete p; return hip_fail(e); }
+    amqft_status st = build_constants(p, logn);
+    if (st == AMQFT_OK) st = prime((int)variant, (int)dtype);
+    if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
+    *out = p;
+    return AMQFT_OK;
+}
+
 amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_t* lengths_host,
                                     const int64_t* offsets_host, amqft_variant variant, amqft_dtype dtype,
                                     unsigned flags) {
@@ -644,7 +693,7 @@ amqft_status amqft_power_loss_grad(amqft_plan p, const void* x, const void* w, v
     if (p->many) return AMQFT_ERR_UNSUPPORTED;
     if (p->batch == 0) return AMQFT_OK;
     if (!x || !w || !grad || !loss) return AMQFT_ERR_INVALID_ARG;
-    if (p->logn < 2 || p->multipass || p->large) return AMQFT_ERR_UNSUPPORTED;
+    if (p->logn < 2 || p->multipass || p->large || p->real_kind >= 0) return AMQFT_ERR_UNSUPPORTED;
     loss_launch a{};
     a.variant = p->variant;
     a.dtype = p->dtype;
@@ -729,7 +778,15 @@ amqft_status amqft_plan_destroy(amqft_plan p) {
 
 amqft_status amqft_plan_describe(amqft_plan p, char* buf, size_t len) {
     if (!p || !buf || len == 0) return AMQFT_ERR_INVALID_ARG;
-    if (p->many) {
+    if (p->real_kind >= 0) {
+        static const char* kinds[3] = {"REAL_RDFT", "REAL_DCT0", "REAL_DST0"};
+        int threads = 0, spw = 1;
+        size_t lds = 0;
+        lds_shape(p->logn, p->dtype, &threads, &spw, &lds);
+        snprintf(buf, len, "amqft_real_kernel<%d, %s, %s> grid=%lld block=%d lds=%zu", p->variant,
+                 p->dtype == AMQFT_C128 ? "double" : "float", kinds[p->real_kind],
+                 (long long)(((p->batch + 1) / 2 + spw - 1) / spw), threads, lds);
+    } else if (p->many) {
         int nclass = 0;
         for (auto& c : p->classes) nclass += c.sub ? 1 : 0;
         snprintf(buf, len, "many-length plan: %lld signals, persistent kernel grid=%d items=%d, %d long-length classes",

@@ -58,6 +58,20 @@ struct loss_launch {
     int onthefly;
 };
 
+// Real transforms (RDFT, DCT-0, DST-0) on the LDS engine: two real signals
+// per complex lane.
+enum { REAL_RDFT = 0, REAL_DCT0 = 1, REAL_DST0 = 2 };
+struct real_launch {
+    int variant, dtype, logn, kind;  // dtype 0 (FP64) or 1 (FP32); 2 <= logn <= kMaxLds*
+    int64_t nreal;                   // real signals
+    const void* in;                  // device reals, stride n / n/2+1 / n/2-1 per kind
+    void* out;                       // device: n/2+1 complex / n/2+1 reals / n/2-1 reals per signal
+    const void* ktab;
+    int ktab_log2n;
+    int onthefly;
+};
+hipError_t launch_real(const real_launch& a, hipStream_t stream);
+
 // Fused loss/gradient kernel (forward, |w|^2 weighting, adjoint).
 hipError_t launch_loss(const loss_launch& a, hipStream_t stream);
 hipError_t launch_kA_loss(const loss_launch& a, hipStream_t stream);

@@ -52,6 +52,101 @@ __global__ __launch_bounds__(1024) void amqft_lds_kernel(const S* __restrict__ i
 }
 
 // ---------------------------------------------------------------------------
+// Real transforms on the same recursion (Sec. 3.1 and Sec. 7.4: the CDFT is
+// D_c / D_r, a DCT-0 and a DST-0 and the combine; the RDFT, the DCT-0 and the
+// DST-0 are that code minus some of these steps).  Since every coefficient of
+// the recursion is real, a complex lane carries two real signals: slot s of
+// the batch runs real signals 2s (real part) and 2s + 1 (imaginary part).
+//   REAL_RDFT  in: n reals per signal; D_c / D_r, dct and dst, then
+//              X(k) = C(k) - i D(k) for k = 0 .. n/2: n/2 + 1 complex out
+//   REAL_DCT0  in: s(0 .. n/2) (n/2 + 1 reals); out S(k) = sum_n s(n)
+//              cos(2 pi n k / n), k = 0 .. n/2 (the dct[n] function)
+//   REAL_DST0  in: s(1 .. n/2 - 1) (n/2 - 1 reals); out S(k) = sum_n s(n)
+//              sin(2 pi n k / n), k = 1 .. n/2 - 1 (the dst[n] function)
+// ---------------------------------------------------------------------------
+template <int V, typename R, int KIND>
+__global__ __launch_bounds__(1024) void amqft_real_kernel(const R* __restrict__ in, R* __restrict__ out,
+                                                           const R* __restrict__ ktab, int logn, long long nreal,
+                                                           int kshift, int onthefly) {
+    using VT = variant_traits<V>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = 1 << logn;
+    const int H = N >> 1;
+    const int D = logn - 2;
+    const int Q = 1 << D;
+    const int T = (N >> 4) > 1 ? (N >> 4) : 1;
+    const int spw = blockDim.x / T;
+    const int slot = threadIdx.x / T;
+    const int ltid = threadIdx.x - slot * T;
+    const long long sig = (long long)blockIdx.x * spw + slot;  // complex slot: real signals 2 sig, 2 sig + 1
+    const bool va = 2 * sig < nreal, vb = 2 * sig + 1 < nreal;
+    R* kt = reinterpret_cast<R*>(smem);
+    const size_t kt_bytes = ((size_t)Q * sizeof(R) + 15) & ~(size_t)15;
+    cx<R>* w = reinterpret_cast<cx<R>*>(smem + kt_bytes) + (size_t)slot * (N + T);
+    cx<R>* scr = w + N;
+    const int in_len = KIND == REAL_RDFT ? N : KIND == REAL_DCT0 ? H + 1 : H - 1;
+    const int out_len = KIND == REAL_RDFT ? 2 * (H + 1) : KIND == REAL_DCT0 ? H + 1 : H - 1;
+    const R* xa = in + (va ? 2 * sig : 0) * (long long)in_len;
+    const R* xb = in + (vb ? 2 * sig + 1 : 0) * (long long)in_len;
+    // lane pair (signal a, signal b) of one real index; zero for a missing signal
+    auto pair = [&](int i) { return cx<R>{va ? xa[i] : R(0), vb ? xb[i] : R(0)}; };
+    const cx<R> z0 = {R(0), R(0)};
+
+    load_constants<V, R>(kt, ktab, Q, kshift, onthefly != 0, logn);
+    for (int m = ltid; m < H; m += T) {
+        int pos = m;
+        if (VT::skel_a && m > 0) {
+            const int j = __ffs(m) - 1;
+            pos = (1 << (D - j)) + (m >> (j + 1));
+        }
+        if (KIND == REAL_RDFT) {
+            const cx<R> a = pair(m), b = pair(m == 0 ? H : N - m);
+            if (m == 0) {
+                w[0] = a;  // c(0)
+                w[H] = b;  // c(N/2)
+            } else {
+                w[pos] = a + b;
+                w[H + pos] = a - b;
+            }
+        } else if (KIND == REAL_DCT0) {
+            if (m == 0) {
+                w[0] = pair(0);
+                w[H] = pair(H);
+            } else {
+                w[pos] = pair(m);
+                w[H + pos] = z0;
+            }
+        } else {
+            if (m == 0) {
+                w[0] = z0;
+                w[H] = z0;
+            } else {
+                w[pos] = z0;
+                w[H + pos] = pair(m - 1);
+            }
+        }
+    }
+    __syncthreads();
+    core<V, R>(w, kt, scr, ltid, T, D, H);
+    R* ya = out + (va ? 2 * sig : 0) * (long long)out_len;
+    R* yb = out + (vb ? 2 * sig + 1 : 0) * (long long)out_len;
+    for (int k = ltid; k <= H; k += T) {
+        const cx<R> C = k == 0 ? w[0] : w[k];
+        const cx<R> Dd = (k == 0 || k == H) ? z0 : w[H + k];
+        if (KIND == REAL_RDFT) {
+            if (va) { ya[2 * k] = C.re; ya[2 * k + 1] = -Dd.re; }
+            if (vb) { yb[2 * k] = C.im; yb[2 * k + 1] = -Dd.im; }
+        } else if (KIND == REAL_DCT0) {
+            if (va) ya[k] = C.re;
+            if (vb) yb[k] = C.im;
+        } else if (k >= 1 && k < H) {
+            if (va) ya[k - 1] = Dd.re;
+            if (vb) yb[k - 1] = Dd.im;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // fused loss and gradient, loss_b = sum_k |w(k) (F x_b)(k)|^2,
 // grad_b = 2 F^H(|w|^2 F x_b) = conj(F conj(2 |w|^2 F x_b)):
 // forward recursion, then the D_c combine of the forward fused with the
@@ -266,6 +361,47 @@ static hipError_t launch_typed(const lds_launch& a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int V, typename R, int KIND>
+static hipError_t launch_real_k(const real_launch& a, hipStream_t stream) {
+    int threads, spw;
+    size_t lds;
+    lds_shape(a.logn, a.dtype, &threads, &spw, &lds);
+    const long long slots = (a.nreal + 1) / 2;
+    const long long grid = (slots + spw - 1) / spw;
+    hipLaunchKernelGGL((amqft_real_kernel<V, R, KIND>), dim3((unsigned)grid), dim3(threads), lds, stream,
+                       static_cast<const R*>(a.in), static_cast<R*>(a.out), static_cast<const R*>(a.ktab), a.logn,
+                       (long long)a.nreal, a.ktab_log2n - a.logn, a.onthefly);
+    return hipGetLastError();
+}
+
+template <int V, typename R>
+static hipError_t launch_real_r(const real_launch& a, hipStream_t s) {
+    switch (a.kind) {
+    case REAL_RDFT: return launch_real_k<V, R, REAL_RDFT>(a, s);
+    case REAL_DCT0: return launch_real_k<V, R, REAL_DCT0>(a, s);
+    default: return launch_real_k<V, R, REAL_DST0>(a, s);
+    }
+}
+
+template <int V>
+static hipError_t launch_real_v(const real_launch& a, hipStream_t s) {
+    return a.dtype == 0 ? launch_real_r<V, double>(a, s) : launch_real_r<V, float>(a, s);
+}
+
+hipError_t launch_real(const real_launch& a, hipStream_t s) {
+    if (a.nreal <= 0) return hipSuccess;
+    switch (a.variant) {
+    case 1: return launch_real_v<1>(a, s);
+    case 2: return launch_real_v<2>(a, s);
+    case 3: return launch_real_v<3>(a, s);
+    case 4: return launch_real_v<4>(a, s);
+    case 5: return launch_real_v<5>(a, s);
+    case 6: return launch_real_v<6>(a, s);
+    case 7: return launch_real_v<7>(a, s);
+    default: return launch_real_v<8>(a, s);
+    }
+}
+
 template <int V, typename S>
 static hipError_t launch_loss_typed(const loss_launch& a, hipStream_t stream) {
     using R = typename storage<S>::R;
@@ -381,9 +517,13 @@ static hipError_t launch_v(const lds_launch& a, hipStream_t s) {
 // graph capture, since attribute calls are not stream work)
 template <int V, typename S>
 static hipError_t prime_typed() {
-    const void* ks[3] = {reinterpret_cast<const void*>(&amqft_lds_kernel<V, S>),
+    using R = typename storage<S>::R;
+    const void* ks[6] = {reinterpret_cast<const void*>(&amqft_lds_kernel<V, S>),
                          reinterpret_cast<const void*>(&amqft_loss_kernel<V, S>),
-                         reinterpret_cast<const void*>(&amqft_persistent_kernel<V, S>)};
+                         reinterpret_cast<const void*>(&amqft_persistent_kernel<V, S>),
+                         reinterpret_cast<const void*>(&amqft_real_kernel<V, R, REAL_RDFT>),
+                         reinterpret_cast<const void*>(&amqft_real_kernel<V, R, REAL_DCT0>),
+                         reinterpret_cast<const void*>(&amqft_real_kernel<V, R, REAL_DST0>)};
     for (const void* k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;

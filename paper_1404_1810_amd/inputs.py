@@ -50,6 +50,15 @@ def complex_uniform(seed: int, batch: int, n: int, start: int = 0) -> np.ndarray
     return _rows(seed, batch, n, "uniform", start)
 
 
+def real_normal(seed: int, batch: int, n: int) -> np.ndarray:
+    """Real signals, i.i.d. N(0,1), float64 (batch, n); signal b from
+    default_rng([seed, b]) like the complex rows."""
+    out = np.empty((batch, n), dtype=np.float64)
+    for b in range(batch):
+        out[b] = np.random.default_rng([seed, b]).standard_normal(n)
+    return out
+
+
 def cfg_fp64_n256(batch: int = 64, n: int = 256) -> np.ndarray:
     """Configuration 1: complex128, 64 x N=256, U[-1,1), seed 0."""
     return complex_uniform(SEEDS["fp64_n256"], batch, n)

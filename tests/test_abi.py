@@ -122,3 +122,18 @@ def test_noalloc_validation(lib):
     assert f(64, 1, 4, 4, 0, None, None, None) == _lib.ERR_INVALID_ARG
     assert f(64, 0, 4, 1, 0, None, None, None) == _lib.OK  # empty batch: nothing to do
     assert f(64, 2, 4, 1, 0, None, None, None) == _lib.ERR_INVALID_ARG  # null buffers
+
+
+@pytest.mark.parametrize("args,status", [((2, 1, 0, 4, 1, 0), _lib.ERR_UNSUPPORTED),        # n below 4
+                                         ((1 << 15, 1, 0, 4, 1, 0), _lib.ERR_UNSUPPORTED),  # above LDS (FP32)
+                                         ((1 << 14, 1, 1, 4, 0, 0), _lib.ERR_UNSUPPORTED),  # above LDS (FP64)
+                                         ((64, 1, 0, 4, 2, 0), _lib.ERR_UNSUPPORTED),       # FP16 storage
+                                         ((64, 1, 0, 4, 1, 4), _lib.ERR_UNSUPPORTED),       # force flag
+                                         ((64, 1, 3, 4, 1, 0), _lib.ERR_INVALID_ARG),       # kind
+                                         ((64, 1, 0, 0, 1, 0), _lib.ERR_INVALID_ARG),       # variant
+                                         ((64, -1, 0, 4, 1, 0), _lib.ERR_INVALID_ARG),      # batch
+                                         ((48, 1, 0, 4, 1, 0), _lib.ERR_NOT_POW2)])
+def test_create_real_validation(lib, args, status):
+    h = ctypes.c_void_p(5)
+    assert lib.amqft_plan_create_real(ctypes.byref(h), *args) == status
+    assert not h.value
