@@ -30,7 +30,8 @@ CSRC = os.path.join(ROOT, "paper_1404_1810_amd", "csrc")
 # sources each kernel family is built from (a traffic measurement is valid
 # only for the exact sources it was taken on)
 KERNEL_SOURCES = {
-    "amqft_kA_kernel": ["amqft_kA.hip", "amqft_leaf.h", "amqft_device.h"],
+    "amqft_kA_kernel": ["amqft_kA.hip", "amqft_kA_passes.h", "amqft_leaf.h", "amqft_device.h"],
+    "amqft_kB_kernel": ["amqft_kB.hip", "amqft_kA_passes.h", "amqft_leaf.h", "amqft_device.h"],
     "amqft_fast_kernel": ["amqft_fast.hip", "amqft_levels.h", "amqft_leaf.h", "amqft_device.h"],
     "amqft_lds_kernel": ["amqft_lds.hip", "amqft_levels.h", "amqft_device.h"],
 }

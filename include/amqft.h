@@ -140,8 +140,8 @@ amqft_status amqft_plan_create_real(amqft_plan *out, int64_t n, int64_t batch,
  * element offsets_host[i]; offsets_host has count+1 entries, is
  * non-decreasing, and offsets_host[i+1] - offsets_host[i] >= lengths_host[i]
  * (signals must not overlap).  Both arrays are host memory and are copied
- * into the plan.  Execution: the short lengths (up to 2^7 for variants 1, 4,
- * 5 and 8, up to 2^12 for the others) run in one persistent launch over a
+ * into the plan.  Execution: the short lengths (up to 2^7 for variants 1, 2,
+ * 4, 5, 6 and 8, up to 2^12 for 3 and 7) run in one persistent launch over a
  * work list sorted longest first; every longer length runs as one batched
  * launch sequence per length class over the same buffer (the classes that
  * need a global workspace on a second stream forked from, and joined back

@@ -608,7 +608,8 @@ amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_
     // persistent work list: the lengths without a compile-time kernel (up to
     // kPersistentMaxLog2, or below 2^8 where one exists), items of up to 256/T
     // signals of one length, longest length first
-    const int pmax = kA_supported(p->variant, 8, p->dtype) ? 7 : kPersistentMaxLog2;
+    const int pmax = (kA_supported(p->variant, 8, p->dtype) || kB_supported(p->variant, 8, p->dtype))
+                         ? 7 : kPersistentMaxLog2;
     std::vector<int> items;  // 4 ints per item
     std::vector<long long> poffs;
     for (int l = pmax; l >= 0; --l) {

@@ -112,6 +112,12 @@ size_t kL_ws_bytes_per_signal(int logn, int dtype);
 hipError_t prime_kL(int variant, int dtype);
 hipError_t launch_kL(const kl_launch& a, hipStream_t stream);
 
+// Skeleton-B kernels for N = 2^8 .. 2^14 (variants 2, 3, 6, 7; FP64 up to
+// 2^13): the transposed program of the skeleton-A kernels (amqft_kB.hip).
+bool kB_supported(int variant, int logn, int dtype);
+hipError_t launch_kB(const lds_launch& a, hipStream_t stream);
+hipError_t prime_kB(int variant, int dtype);
+
 // fused loss / gradient on the same kernels (forward, weighting, adjoint)
 bool kA_loss_supported(int variant, int logn, int dtype);
 

@@ -1,0 +1,789 @@
+// Skeleton-B AM-QFT (variants 2 and 6) for N = 2^8 .. 2^14 as the transposed
+// program of the compile-time skeleton-A kernel (amqft_kA.hip).
+//
+// The DFT matrix is symmetric (eq. qft_0A), so the transposed program of any
+// algorithm for F computes F again.  Transposing the skeleton-A program of
+// variant 4 step by step gives exactly the program of variant 2 (and 8 gives
+// 6): the reflections of D_k^T become the reflections of D_n^F and back,
+// time splits become harmonic interleaves, the multiply of M4 / M8 by
+// 1/(2cos) / 1/(2sin) of theta*n moves to the frequency side, where M2 / M6
+// put it, and their neighbour sums / differences move to the time side
+// (Tables tab:DCT_odd_transformations, tab:DST_odd_transformations); the
+// dct / dst chain's D_n^F becomes the D_k^T that skeleton B applies first
+// (Sec. 5).  The combine X(k) = C(k) -+ i D(k) transposes into D_c plus
+// -i times D_r, and D_c / D_r into the combine: the factor -i rides through
+// the (real-coefficient) DST side exactly.  Every 2-term sum of one program
+// is a 2-term fan-out of the other, so the rounding is that of variant 2
+// (6) evaluated in this order.
+//
+// The kernel therefore runs the passes of amqft_kA.hip in reverse order,
+// each transposed, on the same LDS layouts:
+//   C0^T   load the 16 outputs' positions of the thread's orbit, D_c and -i D_r
+//          of the combine, the three top levels of the chain's D_k^T: blocks
+//          0..2 of both sides into the depth-0 block layout, the level-3 chain
+//          values into the places of blocks 3.. (FOLD's input).
+//   FOLD   the chain's D_k^T for levels 3 .. D-3, one level per barrier
+//          (each thread takes the pairs k and q - k, in place): blocks 3..D-3
+//          and the values of dct[16] / dst[16] (the chain slots).
+//   B0^T   levels 0..2 of dct_to / dst_to: time splits with the M2 / M6
+//          neighbour sums (the transposed B0: the +-1 neighbours of a child
+//          index come from the neighbouring threads' runs, read as a window).
+//   B_k^T  the same for the middle levels.
+//   P3^T   rows of 16 slots, forward and backward in registers (dct_to leaves).
+//   M_k^T  the backward D_n^F butterflies with the 1/(2cos) / 1/(2sin) multiply
+//          on the orbits of the middle passes.
+//   F1^T   the last backward levels on the thread's orbit, the combine of
+//          D_c / D_r transposed, and the store; thread 0 of a signal runs the
+//          chain from dct[16] / dst[16] with the blocks of 4, 2 and 1 points.
+#include <type_traits>
+
+#include "amqft_device.h"
+#include "amqft_internal.h"
+#include "amqft_kA_passes.h"
+#include "amqft_leaf.h"
+
+namespace amqft {
+
+namespace {
+
+// skeleton-A variant whose transposed program is skeleton-B variant VB
+template <int VB>
+struct transposed_of;
+template <> struct transposed_of<2> { static constexpr int V = 4; };
+template <> struct transposed_of<6> { static constexpr int V = 8; };
+
+// transposed butterfly of bfly<SG>: lo = x +- y, hi = (x -+ y) k
+template <int SG, typename R>
+__device__ __forceinline__ void bflyT(cx<R> lo, cx<R> hi, R k, cx<R>& x, cx<R>& y) {
+    const cx<R> h = hi * k;
+    x = lo + h;
+    y = SG == 0 ? lo - h : h - lo;
+}
+
+// i z and -i z (exact)
+template <typename R>
+__device__ __forceinline__ cx<R> mul_i(cx<R> z) { return cx<R>{-z.im, z.re}; }
+
+// transposed combine of one harmonic pair: X(k) = a = C - i D, X(N-k) = b =
+// C + i D, so C' = a + b and D' = i (b - a)
+template <typename R>
+__device__ __forceinline__ void combineT(cx<R> a, cx<R> b, cx<R>& C, cx<R>& Dd) {
+    C = a + b;
+    Dd = mul_i(b - a);
+}
+
+// ---------------------------------------------------------------------------
+// transposed backward levels: the transposes of combine / bwd_levels, on
+// runs of the parent extended by a whole neighbouring run each side (those
+// runs' contributions to the child index are exact; the rest is discarded)
+// ---------------------------------------------------------------------------
+// transposed M^F of one parent position in context SG: the parent value p
+// (= P'[rho]) goes to the hi child entries it was formed from
+template <int V, int SG, typename R>
+__device__ __forceinline__ void mfT(cx<R> p, cx<R>& hm, cx<R>& h0, cx<R>& hp) {
+    if constexpr (V == 4) {
+        if (SG == 0) { h0 = h0 + p; hp = hp + p; }
+        else { hm = hm + p; h0 = h0 + p; }
+    } else {
+        if (SG == 0) { h0 = h0 + p; hm = hm - p; }
+        else { h0 = h0 + p; hp = hp - p; }
+    }
+}
+
+// one transposed level on a parent run of 2n values (no halos: the caller's
+// run is a whole window): L (n), Hh (n) out
+template <int V, int SG, int n, typename R>
+__device__ __forceinline__ void combineT_run(const cx<R>* P, cx<R>* L, cx<R>* Hh) {
+#pragma unroll
+    for (int i = 0; i < n; ++i) Hh[i] = zero<R>();
+#pragma unroll
+    for (int rho = 0; rho < 2 * n; ++rho) {
+        const bool even = (rho & 1) == 0;
+        const int i = even ? rho / 2 : (rho - 1) / 2;
+        if ((SG == 0) == even) {
+            L[i] = P[rho];
+        } else {
+            // forward: P[rho] = mf(H[i-1], H[i], H[i+1]) with H outside [0, n) zero
+            cx<R> hm = zero<R>(), h0 = zero<R>(), hp = zero<R>();
+            mfT<V, SG, R>(P[rho], hm, h0, hp);
+            if (i - 1 >= 0) Hh[i - 1] = Hh[i - 1] + hm;
+            Hh[i] = Hh[i] + h0;
+            if (i + 1 < n) Hh[i + 1] = Hh[i + 1] + hp;
+        }
+    }
+}
+
+// r transposed levels below a parent of context SGB on a window of W runs
+// of 2^r parent values (run w = child index j - W/2 + w): cur[0] holds the
+// W 2^r parent values; out[q] = child q's value at the middle run
+template <int V, int SGB, int r, int t, int W, typename R>
+__device__ __forceinline__ void fwd_levelsT(cx<R> (&cur)[1 << r][W << r]) {
+    if constexpr (t < r) {
+        constexpr bool SW = variant_traits<V>::switches;
+        // before level t: 2^t rows, each a run of W 2^(r-t) values
+        constexpr int nrow = 1 << t;
+        constexpr int len = W << (r - t);
+        cx<R> nxt[1 << r][W << r];
+        sfor<0, nrow>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            // row q of depth t splits into rows 2q (lo) and 2q+1 (hi) of depth t+1;
+            // in bwd_levels the parent of depth t is row q at level r-1-t counted
+            // from the bottom, with context SGB ^ parity(q) for M8
+            constexpr int sg = SGB ^ (SW ? par(q) : 0);
+            combineT_run<V, sg, len / 2, R>(cur[q], nxt[2 * q], nxt[2 * q + 1]);
+        });
+#pragma unroll
+        for (int q = 0; q < 2 * nrow; ++q)
+#pragma unroll
+            for (int e = 0; e < len / 2; ++e) cur[q][e] = nxt[q][e];
+        fwd_levelsT<V, SGB, r, t + 1, W, R>(cur);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// C0^T: one thread per orbit of 16 outputs' positions (the F1 orbit); every
+// entry of blocks 0..2 is written by exactly one thread (C0 read each of them
+// once); the level-3 chain values go to FOLD.
+//   depth-0 block a, entry i: unpadded position H - H / 2^a + i of its half
+//   level-a chain of FOLD: DCT E(k) at H - 2 q_a + k (k < 2 q_a), E(2 q_a) in
+//   the chain slot 8; DST S(k) at H - 2 q_a + k - 1 (k = 1 .. 2 q_a - 1);
+//   q_a = N / 2^(a+2)
+// ---------------------------------------------------------------------------
+template <int LOGN>
+__device__ __forceinline__ int hslot(int side, int p) {
+    using G = kgeo<LOGN>;
+    return side * G::HS + p + (p >> 4);
+}
+
+template <int LOGN, typename R>
+__device__ __forceinline__ void c0T(cx<R>* w, const cx<R> (&raw)[16], int k0, bool conj_in) {
+    using G = kgeo<LOGN>;
+    using L = lds_layout<LOGN>;
+    constexpr int N = G::N, H = G::H, N8 = N / 8, N16 = N / 16;
+    constexpr int B1 = H / 2, B2 = 3 * H / 4, C3 = H - N16;  // starts of blocks 1, 2 and of the level-3 chain
+    cx<R> x[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = conj_in ? cconj(raw[e]) : raw[e];
+    if (k0 > 0) {
+        // res[] order of C0: pairs (lo, hi) = (X(k), X(N-k)) for C[c], Dd[c]
+        constexpr int LO[8] = {0, 8, 1, 9, 2, 10, 3, 11}, HI[8] = {15, 7, 14, 6, 13, 5, 12, 4};
+        cx<R> C[8], Dd[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) combineT(x[LO[c]], x[HI[c]], C[c], Dd[c]);
+        const int kA = k0, kB = N8 - k0, kC = kA + N8, kD = kB + N8;
+        // DCT: levels 0, 1, 2 of the chain's D_k^T
+        cx<R> c1[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c1[i] = C[i] + C[7 - i];
+        stc(w + hslot<LOGN>(0, kA), C[0] - C[7]);
+        stc(w + hslot<LOGN>(0, kB), C[1] - C[6]);
+        stc(w + hslot<LOGN>(0, kC), C[2] - C[5]);
+        stc(w + hslot<LOGN>(0, kD), C[3] - C[4]);
+        const cx<R> c2a = c1[0] + c1[3], c2b = c1[1] + c1[2];
+        stc(w + hslot<LOGN>(0, B1 + kA), c1[0] - c1[3]);
+        stc(w + hslot<LOGN>(0, B1 + kB), c1[1] - c1[2]);
+        stc(w + hslot<LOGN>(0, B2 + kA), c2a - c2b);
+        stc(w + hslot<LOGN>(0, C3 + kA), c2a + c2b);  // E_3(k0)
+        // DST
+        cx<R> s1[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s1[i] = Dd[i] - Dd[7 - i];
+        stc(w + hslot<LOGN>(1, kA - 1), Dd[0] + Dd[7]);
+        stc(w + hslot<LOGN>(1, kB - 1), Dd[1] + Dd[6]);
+        stc(w + hslot<LOGN>(1, kC - 1), Dd[2] + Dd[5]);
+        stc(w + hslot<LOGN>(1, kD - 1), Dd[3] + Dd[4]);
+        const cx<R> s2a = s1[0] - s1[3], s2b = s1[1] - s1[2];
+        stc(w + hslot<LOGN>(1, B1 + kA - 1), s1[0] + s1[3]);
+        stc(w + hslot<LOGN>(1, B1 + kB - 1), s1[1] + s1[2]);
+        stc(w + hslot<LOGN>(1, B2 + kA - 1), s2a + s2b);
+        stc(w + hslot<LOGN>(1, C3 + kA - 1), s2a - s2b);  // S_3(k0)
+    } else {
+        // harmonics N/16 i: res[0] = C(0), res[8] = C(N/2), (res[i], res[16-i]) = (lo, hi) of (C, Dd)[i]
+        cx<R> C[9], Dd[8];
+        C[0] = x[0];
+        C[8] = x[8];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) combineT(x[i], x[16 - i], C[i], Dd[i]);
+        cx<R> E1v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            E1v[i] = C[i] + C[8 - i];
+            stc(w + hslot<LOGN>(0, N16 * i), C[i] - C[8 - i]);  // block 0 at N/16 i
+        }
+        const cx<R> E1_4 = C[4];
+        const cx<R> E2_0 = E1v[0] + E1_4, E2_1 = E1v[1] + E1v[3], E2_2 = E1v[2];
+        stc(w + hslot<LOGN>(0, B1), E1v[0] - E1_4);          // block 1 at 0
+        stc(w + hslot<LOGN>(0, B1 + N16), E1v[1] - E1v[3]);  // block 1 at N/16
+        stc(w + hslot<LOGN>(0, B2), E2_0 - E2_2);            // block 2 at 0
+        stc(w + hslot<LOGN>(0, C3), E2_0 + E2_2);            // E_3(0)
+        stc(w + L::chain(8), E2_1);                          // E_3(N/16): the top of the level-3 chain
+        // DST
+        cx<R> D1v[4];
+#pragma unroll
+        for (int i = 1; i < 4; ++i) {
+            stc(w + hslot<LOGN>(1, N16 * i - 1), Dd[i] + Dd[8 - i]);  // block 0 at N/16 i
+            D1v[i] = Dd[i] - Dd[8 - i];
+        }
+        stc(w + hslot<LOGN>(1, 4 * N16 - 1), Dd[4]);                  // block 0 at N/4
+        stc(w + hslot<LOGN>(1, B1 + N16 - 1), D1v[1] + D1v[3]);       // block 1 at N/16
+        stc(w + hslot<LOGN>(1, B1 + 2 * N16 - 1), D1v[2]);            // block 1 at N/8
+        stc(w + hslot<LOGN>(1, B2 + N16 - 1), D1v[1] - D1v[3]);       // block 2 at N/16
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FOLD: D_k^T of the chain for levels a = 3 .. D-3 (C0 walked these levels
+// along each harmonic's reflection path; here they are summed level by
+// level).  Per level, thread k takes the pairs of k and q - k; the last level
+// writes the dct[16] / dst[16] values into the chain slots.
+// ---------------------------------------------------------------------------
+template <int LOGN, typename R>
+__device__ __forceinline__ void fold(cx<R>* wall, int tid) {
+    using G = kgeo<LOGN>;
+    using L = lds_layout<LOGN>;
+    constexpr int H = G::H, D = G::D;
+    const int s = tid / G::T, k = tid - s * G::T;
+    cx<R>* w = wall + s * G::SL;
+    sfor<3, D - 2>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr int q = G::N >> (a + 2);
+        constexpr bool last = a == D - 3;
+        constexpr int E0 = H - 2 * q;  // E(k) at E0 + k
+        if (k <= q / 2) {
+            // DCT side
+            auto putE = [&](int i, cx<R> v) {  // E_{a+1}(i), i < q
+                if (last) stc(w + L::chain(i), v);
+                else stc(w + hslot<LOGN>(0, H - q + i), v);
+            };
+            if (k == 0) {
+                const cx<R> e0 = ldc(w + hslot<LOGN>(0, E0)), top = ldc(w + L::chain(8));
+                const cx<R> eq = ldc(w + hslot<LOGN>(0, H - q));
+                stc(w + hslot<LOGN>(0, E0), e0 - top);
+                putE(0, e0 + top);
+                stc(w + L::chain(8), eq);
+            } else if (k < q / 2) {
+                const cx<R> xa = ldc(w + hslot<LOGN>(0, E0 + k)), xb = ldc(w + hslot<LOGN>(0, H - k));
+                const cx<R> xc = ldc(w + hslot<LOGN>(0, H - q - k)), xd = ldc(w + hslot<LOGN>(0, H - q + k));
+                stc(w + hslot<LOGN>(0, E0 + k), xa - xb);
+                putE(k, xa + xb);
+                stc(w + hslot<LOGN>(0, H - q - k), xc - xd);
+                putE(q - k, xc + xd);
+            } else {
+                const cx<R> xa = ldc(w + hslot<LOGN>(0, E0 + k)), xb = ldc(w + hslot<LOGN>(0, H - k));
+                stc(w + hslot<LOGN>(0, E0 + k), xa - xb);
+                putE(k, xa + xb);
+            }
+            // DST side: S(k) at E0 + k - 1
+            auto putS = [&](int i, cx<R> v) {  // S_{a+1}(i), i = 1 .. q-1
+                if (last) stc(w + L::chain(8 + i), v);
+                else stc(w + hslot<LOGN>(1, H - q + i - 1), v);
+            };
+            if (k >= 1 && k < q / 2) {
+                const cx<R> xa = ldc(w + hslot<LOGN>(1, E0 + k - 1)), xb = ldc(w + hslot<LOGN>(1, H - k - 1));
+                const cx<R> xc = ldc(w + hslot<LOGN>(1, H - q - k - 1)), xd = ldc(w + hslot<LOGN>(1, H - q + k - 1));
+                stc(w + hslot<LOGN>(1, E0 + k - 1), xa + xb);
+                putS(k, xa - xb);
+                stc(w + hslot<LOGN>(1, H - q - k - 1), xc + xd);
+                putS(q - k, xc - xd);
+            } else if (k == q / 2) {
+                const cx<R> xa = ldc(w + hslot<LOGN>(1, E0 + k - 1)), xb = ldc(w + hslot<LOGN>(1, H - k - 1));
+                stc(w + hslot<LOGN>(1, E0 + k - 1), xa + xb);
+                putS(k, xa - xb);
+            }
+        }
+        __syncthreads();
+    });
+}
+
+// ---------------------------------------------------------------------------
+// B0^T: levels 0..2 of dct_to / dst_to on both sides; thread = position p of
+// the depth-3 layout (as in B0): it reads the depth-0 runs of its child index
+// j and of j -+ 1 (the neighbours' runs carry the +-1 neighbour terms of the
+// time-side M2 / M6 relations) and writes its child index in the 8 rows.
+// ---------------------------------------------------------------------------
+template <int VA, int LOGN, typename R>
+__device__ __forceinline__ void b0T_pass(cx<R>* wall, int tid) {
+    using G = kgeo<LOGN>;
+    constexpr bool SW = variant_traits<VA>::switches;
+    constexpr int LW3 = ilog2c(G::W3);
+    const int s = tid / G::T, p = tid - s * G::T;
+    int a = 0, j = 0, sp = 1;
+    int off1 = 0;
+    if constexpr (G::NP == 0) {
+        const int e = p - 1;
+        const int b = e < 8 ? 0 : e < 12 ? 1 : e < 14 ? 2 : 3;
+        sp = 8 >> b;
+        j = e - (16 - 2 * sp);
+        a = b;
+        off1 = pad(p);
+    } else {
+        using M0 = mpass<LOGN, 0>;
+        constexpr int r0 = M0::r, G0 = M0::GL;
+        if (p < (1 << r0)) {
+            const int e = p - 1;
+            const int b = __clz(~(e << (32 - r0)));
+            sp = (1 << (r0 - 1)) >> b;
+            j = e - ((1 << r0) - 2 * sp);
+            a = LW3 - r0 + b;
+            off1 = 17 * ((e + 1) * (G0 / 16)) + 16;
+        } else {
+            const int pp = p - (1 << r0);
+            a = __clz(~(pp << (32 - LW3)));
+            j = pp - (G::W3 - (G::W3 >> a));
+            sp = G::W3 >> (a + 1);
+            off1 = pad(p);
+        }
+    }
+    const bool act = p > 0;
+    cx<R> cur[2][8][24];
+    if (act) {
+        cx<R>* ws = wall + s * G::SL;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int jj = j - 1 + d;
+            const bool in = jj >= 0 && jj < sp;
+            const int ob = pad(G::H - (G::H >> a) + 8 * (in ? jj : 0));
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const cx<R> v0 = ldc(ws + ob + e), v1 = ldc(ws + G::HS + ob + e);
+                cur[0][0][8 * d + e] = in ? v0 : zero<R>();
+                cur[1][0][8 * d + e] = in ? v1 : zero<R>();
+            }
+        }
+    }
+    __syncthreads();
+    if (act) {
+        fwd_levelsT<VA, 0, 3, 0, 3, R>(cur[0]);
+        fwd_levelsT<VA, 1, 3, 0, 3, R>(cur[1]);
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int hq = side ^ (SW ? par(q) : 0);
+                stc(wall + s * G::SL + hq * G::HS + q * G::W3P + off1, cur[side][q][1]);
+            }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// B_K^T: forward levels l0 .. l0 + r - 1 of pass K (the transposed B_K)
+// ---------------------------------------------------------------------------
+template <int VA, int LOGN, int K, typename R>
+__device__ __forceinline__ void bT_pass(cx<R>* wall, int tid) {
+    using G = kgeo<LOGN>;
+    using M = mpass<LOGN, K>;
+    constexpr bool SW = variant_traits<VA>::switches;
+    constexpr int NV = M::NV, IT = M::IT, LG = ilog2c(M::GL);
+    cx<R> cur[IT][NV][3 * NV];
+    int off1[IT];
+    task tk[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        tk[it] = mtask<LOGN, K>(it, tid);
+        const task t = tk[it];
+        off1[it] = 0;
+        if (t.m > 0) {
+            const int wm = t.m - 1;
+            const int a = __clz(~(wm << (32 - LG)));
+            const int j = wm - (M::GL - (M::GL >> a));
+            const int sp = M::GL >> (a + 1);
+            int off[3];
+            child_offsets<LOGN, K>(a, j, sp, off);
+            off1[it] = off[1];
+            const cx<R>* src = wall + t.s * G::SL + t.h * G::HS + t.P * M::WP;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int jj = j - 1 + d;
+                const bool in = jj >= 0 && jj < sp;
+                const int base = pad(NV * (in ? t.m - 1 + d : t.m));
+#pragma unroll
+                for (int e = 0; e < NV; ++e) {
+                    const cx<R> v = ldc(src + base + e);
+                    cur[it][0][NV * d + e] = in ? v : zero<R>();
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const task t = tk[it];
+        if (t.m > 0) {
+            if (t.h == 0) fwd_levelsT<VA, 0, M::r, 0, 3, R>(cur[it]);
+            else fwd_levelsT<VA, 1, M::r, 0, 3, R>(cur[it]);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const int hq = t.h ^ (SW ? par(q) : 0);
+                stc(wall + t.s * G::SL + hq * G::HS + (t.P * NV + q) * M::GP + off1[it], cur[it][q][1]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// whole sub-blocks of a row of 2^r slots, transposed rowk: o = the blocks'
+// time values, block-contiguous (block of sz points at 2^r - 2 sz); s[e-1] =
+// slot e receives the spectra (dct_to / dst_to of variant VB)
+template <int VB, int SG, int r, typename R>
+__device__ __forceinline__ void rowkT(const cx<R>* o, cx<R>* s, const R* kt, int D) {
+    sfor<0, r>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        constexpr int sz = 1 << (r - 1 - b);
+        cx<R> blk[sz];
+#pragma unroll
+        for (int i = 0; i < sz; ++i) blk[i] = o[(1 << r) - 2 * sz + i];
+        leaf::to<VB, sz, SG, R>(blk, kt, D);
+#pragma unroll
+        for (int i = 0; i < sz; ++i) s[((2 * i + 1) << b) - 1] = blk[i];
+    });
+}
+
+// P3^T: rows of 16 at depth D-3, in place
+template <int VB, int LOGN, typename R>
+__device__ __forceinline__ void p3T_pass(cx<R>* wall, const R* kt, int tid) {
+    using G = kgeo<LOGN>;
+    constexpr int NR = 1 << (G::D - 3);
+    const int h = tid / (G::SPW * NR);
+    const int rem = tid - h * (G::SPW * NR);
+    const int s = rem / NR, R7 = rem - s * NR;
+    cx<R>* row = wall + s * G::SL + h * G::HS + 17 * R7;
+    cx<R> in[15], o[15];
+#pragma unroll
+    for (int e = 0; e < 15; ++e) in[e] = ldc(row + e + 1);
+    if (h == 0) rowkT<VB, 0, 4, R>(in, o, kt, G::D);
+    else rowkT<VB, 1, 4, R>(in, o, kt, G::D);
+#pragma unroll
+    for (int e = 0; e < 15; ++e) stc(row + e + 1, o[e]);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// M_K^T: backward levels l0 + r - 1 .. l0 on the orbits of pass K
+// ---------------------------------------------------------------------------
+template <int VA, int LOGN, int K, int H, typename R>
+__device__ __forceinline__ void orbitT_compute(const R* kf, const cx<R> (&c)[mpass<LOGN, K>::NV], int m0,
+                                               cx<R> (&v)[mpass<LOGN, K>::NV]) {
+    using G = kgeo<LOGN>;
+    using M = mpass<LOGN, K>;
+    constexpr bool SW = variant_traits<VA>::switches;
+    constexpr int NV = M::NV, r = M::r;
+    const R* kw = kf + G::kfbase(K) + (m0 - 1);
+    // cur[q][rho]: after level t of orbit_compute row q holds entries rho < KK/2
+    cx<R> cur[NV][NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) cur[q][0] = c[q];
+    sfor<0, r>([&](auto tc) {
+        constexpr int t = r - 1 - decltype(tc)::value;  // undo level t
+        constexpr int KK = NV >> t;
+        constexpr int rows = 1 << t;
+        cx<R> prv[NV][NV];
+        sfor<0, rows>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int sg = H ^ (SW ? par(q) : 0);
+#pragma unroll
+            for (int rho = 0; rho < KK / 2; ++rho)
+                bflyT<sg, R>(cur[2 * q][rho], cur[2 * q + 1][rho], kw[G::kft(K, t) + (M::GL - 1) * rho], prv[q][rho],
+                             prv[q][KK - 1 - rho]);
+        });
+#pragma unroll
+        for (int q = 0; q < rows; ++q)
+#pragma unroll
+            for (int rho = 0; rho < KK; ++rho) cur[q][rho] = prv[q][rho];
+    });
+#pragma unroll
+    for (int e = 0; e < NV; ++e) v[e] = cur[0][e];
+}
+
+template <int VA, int VB, int LOGN, int K, typename R>
+__device__ __forceinline__ void orbitT_pass(cx<R>* wall, const R* kt, const R* kf, int tid) {
+    using G = kgeo<LOGN>;
+    using M = mpass<LOGN, K>;
+    constexpr bool SW = variant_traits<VA>::switches;
+    constexpr int NV = M::NV, IT = M::IT;
+    cx<R> c[IT][NV];
+    task tk[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        tk[it] = mtask<LOGN, K>(it, tid);
+        const task t = tk[it];
+        cx<R>* ws = wall + t.s * G::SL;
+        if (t.m > 0) {
+            const int pm = pad(t.m);
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const int hq = t.h ^ (SW ? par(q) : 0);
+                c[it][q] = ldc(ws + hq * G::HS + (t.P * NV + q) * M::GP + pm);  // child row P 2^r + q, slot m
+            }
+        } else {
+            const cx<R>* pb = ws + t.h * G::HS + t.P * M::WP + 16;
+#pragma unroll
+            for (int i = 0; i < NV - 1; ++i) c[it][i] = ldc(pb + 17 * (i + 1) * (M::GL / 16));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const task t = tk[it];
+        cx<R>* base = wall + t.s * G::SL + t.h * G::HS + t.P * M::WP;
+        const int m = t.m;
+        if (m > 0) {
+            cx<R> v[NV];
+            if (t.h == 0) orbitT_compute<VA, LOGN, K, 0, R>(kf, c[it], m, v);
+            else orbitT_compute<VA, LOGN, K, 1, R>(kf, c[it], m, v);
+            const int pa = pad(m), pb = m + ((m + 15) >> 4);
+#pragma unroll
+            for (int i = 0; i < NV / 2; ++i) {
+                stc(base + pa + 2 * M::GP * i, v[2 * i]);              // slot m + 2 G i
+                stc(base + 2 * M::GP * (i + 1) - pb, v[2 * i + 1]);    // slot 2 G (i+1) - m
+            }
+        } else {
+            cx<R> v[NV];
+            if (t.h == 0) rowkT<VB, 0, M::r, R>(c[it], v, kt, G::D);
+            else rowkT<VB, 1, M::r, R>(c[it], v, kt, G::D);
+#pragma unroll
+            for (int e = 1; e < NV; ++e) stc(base + e * M::GP, v[e - 1]);  // slot e G
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// F1^T: levels 2..0 backward on the orbit, transposed D_c / D_r, store
+// ---------------------------------------------------------------------------
+template <int VA, int LOGN, typename R>
+__device__ __forceinline__ void f1T_orbit(const cx<R>* w, const R* kt, int m0, cx<R> (&res)[16]) {
+    using G = kgeo<LOGN>;
+    constexpr bool SW = variant_traits<VA>::switches;
+    constexpr int N8 = G::N / 8, N4 = G::N / 4;
+    const R k0[4] = {kt[m0], kt[N8 - m0], kt[N8 + m0], kt[N4 - m0]};
+    const R k1[2] = {kt[2 * m0], kt[N4 - 2 * m0]};
+    const R k2 = kt[4 * m0];
+    const int pm = pad(m0);
+    cx<R> cd[2][8];
+    sfor<0, 2>([&](auto sc) {
+        constexpr int side = decltype(sc)::value;
+        cx<R> d3[8];
+        sfor<0, 8>([&](auto pc) {
+            constexpr int P8 = decltype(pc)::value;
+            constexpr int hh = side ^ (SW ? par(P8) : 0);
+            d3[P8] = ldc(w + hh * G::HS + G::W3P * P8 + pm);
+        });
+        cx<R> l2[4][2];
+        sfor<0, 4>([&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            constexpr int sg = side ^ (SW ? par(P) : 0);
+            bflyT<sg, R>(d3[2 * P], d3[2 * P + 1], k2, l2[P][0], l2[P][1]);
+        });
+        cx<R> l1[2][4];
+        sfor<0, 2>([&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            constexpr int sg = side ^ (SW ? par(P) : 0);
+#pragma unroll
+            for (int r = 0; r < 2; ++r) bflyT<sg, R>(l2[2 * P][r], l2[2 * P + 1][r], k1[r], l1[P][r], l1[P][3 - r]);
+        });
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bflyT<side, R>(l1[0][r], l1[1][r], k0[r], cd[side][r], cd[side][7 - r]);
+    });
+    // transposed D_c / D_r: x(m) = c + d, x(N - m) = c - d at the orbit slots
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        res[i] = cd[0][2 * i] + cd[1][2 * i];              // x(m0 + N8 i)
+        res[8 + 7 - i] = cd[0][2 * i] - cd[1][2 * i];      // x(N8 (8 - i) - m0)
+        res[8 + i] = cd[0][2 * i + 1] + cd[1][2 * i + 1];  // x(N8 (i + 1) - m0)
+        res[7 - i] = cd[0][2 * i + 1] - cd[1][2 * i + 1];  // x(m0 + N8 (7 - i))
+    }
+}
+
+// thread 0: the chain from dct[16] / dst[16] (chain slots) with the blocks of
+// 4, 2 and 1 points, then D_c / D_r transposed at the multiples of N/16
+template <int VB, int LOGN, typename R>
+__device__ __forceinline__ void f1T_chain(const cx<R>* w, const R* kt, cx<R> (&res)[16]) {
+    using L = lds_layout<LOGN>;
+    constexpr int D = LOGN - 2;
+    cx<R> E8[9], P[16];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) E8[k] = ldc(w + L::chain(k));
+#pragma unroll
+    for (int k = 9; k < 16; ++k) P[k] = ldc(w + L::chain(k));
+    cx<R> c[9], d[8];
+    {
+        cx<R> E9[5], b8[4];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            E9[k] = E8[k] + E8[8 - k];
+            b8[k] = E8[k] - E8[8 - k];
+        }
+        E9[0] = E8[0] + E8[8];
+        b8[0] = E8[0] - E8[8];
+        E9[4] = E8[4];
+        cx<R> b9[2];
+        const cx<R> E10_0 = E9[0] + E9[4], E10_1 = E9[1] + E9[3], E10_2 = E9[2];
+        b9[0] = E9[0] - E9[4];
+        b9[1] = E9[1] - E9[3];
+        const cx<R> e0 = E10_0 + E10_2, e1 = E10_1;
+        c[4] = E10_0 - E10_2;  // O10
+        c[0] = e0 + e1;
+        c[8] = e0 - e1;        // c(N/2)
+        leaf::to<VB, 4, 0, R>(b8, kt, D);
+        leaf::to<VB, 2, 0, R>(b9, kt, D);
+        c[1] = b8[0];
+        c[3] = b8[1];
+        c[5] = b8[2];
+        c[7] = b8[3];
+        c[2] = b9[0];
+        c[6] = b9[1];
+    }
+    {
+        cx<R> b8[4], E9[4];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            b8[k - 1] = P[8 + k] + P[16 - k];
+            E9[k] = P[8 + k] - P[16 - k];
+        }
+        b8[3] = P[12];
+        cx<R> b9[2];
+        b9[0] = E9[1] + E9[3];
+        d[4] = E9[1] - E9[3];  // E10
+        b9[1] = E9[2];
+        leaf::to<VB, 4, 1, R>(b8, kt, D);
+        leaf::to<VB, 2, 1, R>(b9, kt, D);
+        d[1] = b8[0];
+        d[3] = b8[1];
+        d[5] = b8[2];
+        d[7] = b8[3];
+        d[2] = b9[0];
+        d[6] = b9[1];
+    }
+    res[0] = c[0];
+    res[8] = c[8];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        res[k] = c[k] + d[k];
+        res[16 - k] = c[k] - d[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the kernel (same launch geometry and LDS as amqft_kA_kernel)
+// ---------------------------------------------------------------------------
+template <int VB, typename S, int LOGN>
+__global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kB_kernel(const S* __restrict__ in, S* __restrict__ out,
+                                                                   const typename storage<S>::R* __restrict__ ktab,
+                                                                   long long batch, int kshift, int flags,
+                                                                   const long long* __restrict__ offsets) {
+    using R = typename storage<S>::R;
+    using G = kgeo<LOGN>;
+    constexpr int VA = transposed_of<VB>::V;
+    extern __shared__ __align__(16) unsigned char smem[];
+    R* kt = reinterpret_cast<R*>(smem);
+    R* kf = kt + G::Q;
+    cx<R>* wall = reinterpret_cast<cx<R>*>(smem + (G::Q + G::KF_ALLOC) * sizeof(R));
+    const bool conj_in = flags & 1, conj_out = flags & 2, onthefly = flags & 4;
+    const int tid = threadIdx.x;
+    const int fs = tid / G::T, m0 = tid - fs * G::T;
+    const long long gs = (long long)blockIdx.x * G::SPW + fs;
+    const bool live = gs < batch;
+    long long base = !live ? 0 : offsets ? offsets[gs] : gs * (long long)G::N;
+    constexpr bool WU = G::T >= 64;
+    if constexpr (WU) base = uniform64(base);
+
+    cx<R> raw[16];
+    f1_load<LOGN, S, R, WU>(in + base, m0, raw);
+    fill_constants<VA, LOGN, R>(kt, kf, ktab, kshift, onthefly, tid);
+    cx<R>* w = wall + fs * G::SL;
+    c0T<LOGN, R>(w, raw, m0, conj_in);
+    __syncthreads();
+    fold<LOGN, R>(wall, tid);
+    b0T_pass<VA, LOGN, R>(wall, tid);
+    sfor<0, G::NP>([&](auto kc) { bT_pass<VA, LOGN, decltype(kc)::value, R>(wall, tid); });
+    p3T_pass<VB, LOGN, R>(wall, kt, tid);
+    sfor<0, G::NP>([&](auto kc) { orbitT_pass<VA, VB, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, kt, kf, tid); });
+    if (live) {
+        cx<R> res[16];
+        if (m0 > 0) f1T_orbit<VA, LOGN, R>(w, kt, m0, res);
+        else f1T_chain<VB, LOGN, R>(w, kt, res);
+        c0_store<LOGN, S, R, WU>(out + base, m0, res, conj_out);
+    }
+}
+
+template <int VB, typename S, int LOGN>
+hipError_t launch_kB_n(const lds_launch& a, hipStream_t st) {
+    using R = typename storage<S>::R;
+    using G = kgeo<LOGN>;
+    const int flags = (a.conj_in ? 1 : 0) | (a.conj_out ? 2 : 0) | (a.onthefly ? 4 : 0);
+    const long long grid = (a.batch + G::SPW - 1) / G::SPW;
+    const size_t lds = kA_lds_bytes<R, LOGN>();
+    hipLaunchKernelGGL((amqft_kB_kernel<VB, S, LOGN>), dim3((unsigned)grid), dim3(G::WG), lds, st,
+                       static_cast<const S*>(a.in), static_cast<S*>(a.out), static_cast<const R*>(a.ktab),
+                       (long long)a.batch, a.ktab_log2n - LOGN, flags, static_cast<const long long*>(a.offsets));
+    return hipGetLastError();
+}
+
+template <int VB, typename S>
+hipError_t launch_kB_s(const lds_launch& a, hipStream_t st) {
+    switch (a.logn) {
+    case 8: return launch_kB_n<VB, S, 8>(a, st);
+    case 9: return launch_kB_n<VB, S, 9>(a, st);
+    case 10: return launch_kB_n<VB, S, 10>(a, st);
+    case 11: return launch_kB_n<VB, S, 11>(a, st);
+    case 12: return launch_kB_n<VB, S, 12>(a, st);
+    case 13: return launch_kB_n<VB, S, 13>(a, st);
+    default:
+        if constexpr (std::is_same<S, double2>::value) return hipErrorInvalidValue;
+        else return launch_kB_n<VB, S, 14>(a, st);
+    }
+}
+
+template <int VB, typename S, int LOGN>
+hipError_t prime_kB_n() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kB_kernel<VB, S, LOGN>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    constexpr int LMAX = std::is_same<S, double2>::value ? 13 : 14;
+    if constexpr (LOGN < LMAX) {
+        if (e == hipSuccess) e = prime_kB_n<VB, S, LOGN + 1>();
+    }
+    return e;
+}
+
+template <int VB>
+hipError_t launch_kB_v(const lds_launch& a, hipStream_t st) {
+    switch (a.dtype) {
+    case 0: return launch_kB_s<VB, double2>(a, st);
+    case 1: return launch_kB_s<VB, float2>(a, st);
+    case 2: return launch_kB_s<VB, __half2>(a, st);
+    default: return launch_kB_s<VB, bf16x2>(a, st);
+    }
+}
+
+template <int VB>
+hipError_t prime_kB_v(int dtype) {
+    switch (dtype) {
+    case 0: return prime_kB_n<VB, double2, 8>();
+    case 1: return prime_kB_n<VB, float2, 8>();
+    case 2: return prime_kB_n<VB, __half2, 8>();
+    default: return prime_kB_n<VB, bf16x2, 8>();
+    }
+}
+
+}  // namespace
+
+bool kB_supported(int variant, int logn, int dtype) {
+    if (variant != 2 && variant != 6) return false;
+    if (dtype == 0) return logn >= 8 && logn <= 13;
+    return logn >= 8 && logn <= 14;
+}
+
+hipError_t launch_kB(const lds_launch& a, hipStream_t st) {
+    if (a.batch <= 0) return hipSuccess;
+    if (!kB_supported(a.variant, a.logn, a.dtype)) return hipErrorInvalidValue;
+    return a.variant == 2 ? launch_kB_v<2>(a, st) : launch_kB_v<6>(a, st);
+}
+
+hipError_t prime_kB(int variant, int dtype) {
+    if (variant == 2) return prime_kB_v<2>(dtype);
+    if (variant == 6) return prime_kB_v<6>(dtype);
+    return hipSuccess;
+}
+
+}  // namespace amqft

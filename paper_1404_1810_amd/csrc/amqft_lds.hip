@@ -544,6 +544,7 @@ static hipError_t prime_v(int dtype) {
 hipError_t prime_lds(int variant, int dtype) {
     hipError_t e = prime_fast(variant, dtype);
     if (e == hipSuccess) e = prime_kA(variant, dtype);
+    if (e == hipSuccess) e = prime_kB(variant, dtype);
     if (e != hipSuccess) return e;
     switch (variant) {
     case 1: return prime_v<1>(dtype);
@@ -596,6 +597,10 @@ void describe_lds(const lds_launch& a, char* buf, size_t len) {
         lds = kA_lds(a.variant, a.logn, a.dtype);
         snprintf(buf, len, "amqft_kA_kernel<%d, %s, %d> grid=%lld block=%d lds=%zu", a.variant, sname, a.logn,
                  (long long)((a.batch + spw - 1) / spw), threads, lds);
+    } else if (!a.generic && kB_supported(a.variant, a.logn, a.dtype)) {
+        kA_shape(a.logn, a.dtype, &threads, &spw, &lds);  // the same geometry and LDS as the skeleton-A kernel
+        snprintf(buf, len, "amqft_kB_kernel<%d, %s, %d> grid=%lld block=%d lds=%zu", a.variant, sname, a.logn,
+                 (long long)((a.batch + spw - 1) / spw), threads, lds);
     } else if (!a.generic && fast_supported(a.logn, a.dtype)) {
         fast_shape(a.logn, a.dtype, &threads, &spw, &lds);
         snprintf(buf, len, "amqft_fast_kernel<%d, %s, %d> grid=%lld block=%d lds=%zu", a.variant, sname, a.logn,
@@ -611,6 +616,7 @@ void describe_lds(const lds_launch& a, char* buf, size_t len) {
 
 hipError_t launch_lds(const lds_launch& a, hipStream_t s) {
     if (!a.generic && kA_supported(a.variant, a.logn, a.dtype)) return launch_kA(a, s);
+    if (!a.generic && kB_supported(a.variant, a.logn, a.dtype)) return launch_kB(a, s);
     if (!a.generic && fast_supported(a.logn, a.dtype)) return launch_fast(a, s);
     switch (a.variant) {
     case 1: return launch_v<1>(a, s);

@@ -1,0 +1,98 @@
+// Driver of the CPU emulation of the amqft kernels (test infrastructure):
+//   amqft_emu PATH VARIANT DTYPE LOGN BATCH CONJ IN OUT
+// PATH: lds (the dispatch of launch_lds: compile-time kernels where they
+// exist), generic (the level engine), large (the top/rows/back/bchain
+// kernels of variants 4 and 8 over malloc'd workspaces), tkernel (the
+// transposed compile-time kernel).  DTYPE 0 = complex FP64, 1 = complex FP32.
+// IN / OUT: raw interleaved complex arrays of BATCH x 2^LOGN values.
+// The constant table is built on the host in long double and rounded once.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "amqft_device.h"
+#include "amqft_internal.h"
+
+using namespace amqft;
+
+static double family_value(int fam, long p, long n) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double a = 2.0L * pi * (long double)p / (long double)n;
+    long double v;
+    switch (fam) {
+    case 0: v = 2.0L * cosl(a); break;
+    case 1: v = 1.0L / (2.0L * cosl(a)); break;
+    case 2: v = 2.0L * sinl(a); break;
+    default: v = 1.0L / (2.0L * sinl(a)); break;
+    }
+    return (double)v;
+}
+
+int main(int argc, char** argv) {
+    if (argc != 9) {
+        std::fprintf(stderr, "usage: %s PATH VARIANT DTYPE LOGN BATCH CONJ IN OUT\n", argv[0]);
+        return 2;
+    }
+    const std::string path = argv[1];
+    const int variant = std::atoi(argv[2]), dtype = std::atoi(argv[3]), logn = std::atoi(argv[4]);
+    const long batch = std::atol(argv[5]);
+    const int conj = std::atoi(argv[6]);
+    const long n = 1L << logn;
+    const size_t esz = dtype == 0 ? 16 : 8, rsz = esz / 2;
+    std::vector<unsigned char> in((size_t)batch * n * esz), out(in.size(), 0xFF);
+    FILE* f = std::fopen(argv[7], "rb");
+    if (!f || std::fread(in.data(), 1, in.size(), f) != in.size()) { std::fprintf(stderr, "bad input\n"); return 2; }
+    std::fclose(f);
+    const long q = n / 4 > 1 ? n / 4 : 1;
+    std::vector<unsigned char> kt((size_t)q * rsz, 0);
+    for (long p = 1; p < q; ++p) {
+        const double v = family_value(const_family(variant), p, n);
+        if (dtype == 0) std::memcpy(&kt[p * rsz], &v, 8);
+        else { const float fv = (float)v; std::memcpy(&kt[p * rsz], &fv, 4); }
+    }
+    hipError_t e = hipSuccess;
+    if (path == "lds" || path == "generic" || path == "tkernel") {
+        lds_launch a{};
+        a.variant = variant;
+        a.dtype = dtype;
+        a.logn = logn;
+        a.batch = batch;
+        a.in = in.data();
+        a.out = out.data();
+        a.ktab = kt.data();
+        a.ktab_log2n = logn;
+        a.conj_in = conj;
+        a.conj_out = conj;
+        a.generic = path == "generic";
+        e = path == "tkernel" ? launch_kB(a, nullptr) : launch_lds(a, nullptr);
+    } else if (path == "large") {
+        kl_launch k{};
+        k.variant = variant;
+        k.dtype = dtype;
+        k.logn = logn;
+        k.batch = batch;
+        k.chunk = batch;
+        std::vector<unsigned char> ws1((size_t)batch * n * esz), ws2(ws1.size()), wsc((size_t)batch * 16 * esz);
+        k.in = in.data();
+        k.out = out.data();
+        k.ws1 = ws1.data();
+        k.ws2 = ws2.data();
+        k.wsc = wsc.data();
+        k.ktab = kt.data();
+        k.conj_in = conj;
+        k.conj_out = conj;
+        e = launch_kL(k, nullptr);
+    } else {
+        std::fprintf(stderr, "unknown path %s\n", path.c_str());
+        return 2;
+    }
+    if (e != hipSuccess) { std::fprintf(stderr, "launch failed %d\n", (int)e); return 3; }
+    if (emu::g_races.load() > 0) { std::fprintf(stderr, "%ld LDS races\n", emu::g_races.load()); return 4; }
+    f = std::fopen(argv[8], "wb");
+    if (!f || std::fwrite(out.data(), 1, out.size(), f) != out.size()) { std::fprintf(stderr, "bad output\n"); return 2; }
+    std::fclose(f);
+    return 0;
+}
