@@ -1,0 +1,68 @@
+"""CPU emulation of the HIP kernel sources (no GPU): the compile-time kernels
+of both skeletons, the large-N path and the generic engines, compiled for the
+host with the shim of tests/emu under AddressSanitizer and UBSan, every
+workgroup's LDS filled with NaN bytes, LDS accesses checked for races between
+barriers and buffer accesses for their bounds, and the results compared with
+the oracle under the pins of the GPU tests.  This is how a kernel is run
+before its first GPU launch; here it guards the sources on every CPU run."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import bound, rel, truth
+from paper_1404_1810_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "emu"))
+
+
+@pytest.fixture(scope="module")
+def emu_exe():
+    import build_emu
+    try:
+        return build_emu.build()
+    except FileNotFoundError:  # pragma: no cover
+        pytest.skip("host clang++ not available")
+
+
+CASES = [
+    # (path, variant, dtype 0 = FP64 / 1 = FP32, log2 N, batch, conjugated in and out)
+    ("lds", 4, 1, 12, 2, 0),     # amqft_kA_kernel, headline geometry
+    ("lds", 4, 0, 13, 1, 0),
+    ("lds", 1, 1, 14, 1, 0),     # recurrences across several waves
+    ("lds", 5, 0, 9, 3, 1),      # two signals per workgroup, adjoint
+    ("lds", 8, 0, 11, 2, 0),
+    ("tkernel", 2, 0, 8, 5, 0),  # amqft_kB_kernel: four signals per workgroup
+    ("tkernel", 2, 0, 11, 2, 1),
+    ("tkernel", 2, 1, 12, 2, 0),
+    ("tkernel", 6, 0, 10, 2, 0),
+    ("tkernel", 6, 1, 8, 3, 1),
+    ("tkernel", 2, 1, 14, 1, 1),
+    ("large", 4, 0, 11, 2, 0),   # top / rows / back / bchain, rows sharing workgroups
+    ("large", 8, 0, 12, 1, 1),
+    ("generic", 3, 0, 10, 3, 0),  # level engine
+    ("lds", 7, 0, 12, 1, 0),     # amqft_fast_kernel
+]
+
+
+@pytest.mark.parametrize("path,variant,dtype,logn,batch,conj", CASES)
+def test_kernel_source_on_cpu(emu_exe, tmp_path, path, variant, dtype, logn, batch, conj):
+    n = 1 << logn
+    x = inputs.complex_normal(7 + logn, batch, n).astype(np.complex128 if dtype == 0 else np.complex64)
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    x.tofile(fin)
+    r = subprocess.run([emu_exe, path, str(variant), str(dtype), str(logn), str(batch), str(conj), fin, fout],
+                       capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1"))
+    assert r.returncode == 0, r.stderr[-4000:]
+    y = np.fromfile(fout, dtype=x.dtype).reshape(batch, n)
+    src = np.conj(x) if conj else x
+    ref = truth(src)
+    if conj:
+        ref = np.conj(ref)
+    b = bound(variant, dtype == 0, src, ref if not conj else np.conj(ref))
+    assert b is not None, "every emulated case is chosen where its variant has a pin"
+    assert rel(y, ref) <= b, (rel(y, ref), b)
