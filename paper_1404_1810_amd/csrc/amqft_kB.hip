@@ -1,10 +1,10 @@
-// Skeleton-B AM-QFT (variants 2 and 6) for N = 2^8 .. 2^14 as the transposed
+// Skeleton-B AM-QFT (variants 2, 3, 6, 7) for N = 2^8 .. 2^14 as the transposed
 // program of the compile-time skeleton-A kernel (amqft_kA.hip).
 //
 // The DFT matrix is symmetric (eq. qft_0A), so the transposed program of any
 // algorithm for F computes F again.  Transposing the skeleton-A program of
-// variant 4 step by step gives exactly the program of variant 2 (and 8 gives
-// 6): the reflections of D_k^T become the reflections of D_n^F and back,
+// variant 4 step by step gives exactly the program of variant 2 (8 gives 6,
+// 1 gives 3, 5 gives 7): the reflections of D_k^T become the reflections of D_n^F and back,
 // time splits become harmonic interleaves, the multiply of M4 / M8 by
 // 1/(2cos) / 1/(2sin) of theta*n moves to the frequency side, where M2 / M6
 // put it, and their neighbour sums / differences move to the time side
@@ -51,6 +51,8 @@ template <int VB>
 struct transposed_of;
 template <> struct transposed_of<2> { static constexpr int V = 4; };
 template <> struct transposed_of<6> { static constexpr int V = 8; };
+template <> struct transposed_of<3> { static constexpr int V = 1; };
+template <> struct transposed_of<7> { static constexpr int V = 5; };
 
 // transposed butterfly of bfly<SG>: lo = x +- y, hi = (x -+ y) k
 template <int SG, typename R>
@@ -422,6 +424,286 @@ __device__ __forceinline__ void bT_pass(cx<R>* wall, int tid) {
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// M3 / M7: the transposes of the M1 / M5 recurrences.  With the sign pattern
+// D = diag((-1)^i) of M1 and the halving Hv of the first term in scan order,
+// the backward M^F of M1 / M5 is g = D T D Hv h (T an inclusive prefix or
+// suffix sum along the hi child); its transpose is Hv D T^T D: the same lane
+// scan run in the other direction, the halving applied after it.  That is
+// the time-side recurrence of M3 / M7, the last term halved (Tables
+// tab:DCT_odd_transformations, tab:DST_odd_transformations).
+// ---------------------------------------------------------------------------
+// one transposed level for one lane: parent entries P[0 .. 2n) -> lo child
+// L[0 .. n), hi child Hh[0 .. n) (segment position pos of nl lanes)
+template <int VA, int SG, int n, int MAXL, typename R>
+__device__ __forceinline__ void rec_split(const cx<R>* P, cx<R>* L, cx<R>* Hh, int pos, int nl) {
+    using RD = rec_dir<VA, SG>;
+    constexpr bool TASC = !RD::asc;
+    const int len = nl * n;
+    cx<R> raw[n], u[n], loc[n];
+#pragma unroll
+    for (int e = 0; e < n; ++e) {
+        L[e] = SG == 0 ? P[2 * e] : P[2 * e + 1];
+        raw[e] = SG == 0 ? P[2 * e + 1] : P[2 * e];
+        const int i = pos * n + e;
+        u[e] = (RD::alt && (i & 1)) ? cx<R>{-raw[e].re, -raw[e].im} : raw[e];
+    }
+    cx<R> tot;
+    if constexpr (TASC) {
+        loc[0] = u[0];
+#pragma unroll
+        for (int e = 1; e < n; ++e) loc[e] = loc[e - 1] + u[e];
+        tot = loc[n - 1];
+    } else {
+        loc[n - 1] = u[n - 1];
+#pragma unroll
+        for (int e = n - 2; e >= 0; --e) loc[e] = loc[e + 1] + u[e];
+        tot = loc[0];
+    }
+    cx<R> carry, own = tot;
+    if constexpr (n == 1) pair_excl<TASC, MAXL, R>(u[0], pos, nl, carry, own);
+    else carry = seg_excl<TASC, MAXL, R>(tot, pos, nl);
+#pragma unroll
+    for (int e = 0; e < n; ++e) {
+        const int i = pos * n + e;
+        cx<R> g = (n == 1 ? own : loc[e]) + carry;
+        if (RD::alt && (i & 1)) g = cx<R>{-g.re, -g.im};
+        if (len > 1 && (RD::asc ? i == 0 : i == len - 1)) g = g * R(0.5);
+        Hh[e] = len == 1 ? raw[e] : g;  // L = 8 base: no M step
+    }
+}
+
+// r transposed recurrence levels below a parent of context SGB for one lane:
+// cur[0][0 .. 2^r) = the lane's parent entries in; cur[q][0] = child q out
+template <int VA, int SGB, int r, int t, int MAXL, typename R>
+__device__ __forceinline__ void rec_levelsT(cx<R> (&cur)[1 << r][1 << r], int pos, int nl) {
+    if constexpr (t < r) {
+        constexpr bool SW = variant_traits<VA>::switches;
+        constexpr int nrow = 1 << t, n = 1 << (r - 1 - t);
+        cx<R> nxt[1 << r][1 << r];
+        sfor<0, nrow>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            constexpr int sg = SGB ^ (SW ? par(q) : 0);
+            rec_split<VA, sg, n, MAXL, R>(cur[q], nxt[2 * q], nxt[2 * q + 1], pos, nl);
+        });
+#pragma unroll
+        for (int q = 0; q < 2 * nrow; ++q)
+#pragma unroll
+            for (int e = 0; e < n; ++e) cur[q][e] = nxt[q][e];
+        rec_levelsT<VA, SGB, r, t + 1, MAXL, R>(cur, pos, nl);
+    }
+}
+
+// B_K^T for M3 / M7 (the transposed bpass_rec: same lane remapping)
+template <int VA, int LOGN, int K, typename R>
+__device__ __forceinline__ void bT_rec_pass(cx<R>* wall, int tid) {
+    using G = kgeo<LOGN>;
+    using M = mpass<LOGN, K>;
+    constexpr bool SW = variant_traits<VA>::switches;
+    constexpr int NV = M::NV, IT = M::IT, LG = ilog2c(M::GL), MAXL = M::GL / 2;
+    cx<R> cur[IT][NV][NV];
+    task tk[IT];
+    int jj[IT], spp[IT], off1[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        tk[it] = mtask<LOGN, K>(it, tid);
+        const task t = tk[it];
+        const int wm = t.m;
+        const int a = __clz(~(wm << (32 - LG)));
+        const bool act = wm < M::GL - 1;
+        const int j = act ? wm - (M::GL - (M::GL >> a)) : 0;
+        const int sp = act ? M::GL >> (a + 1) : 0;
+        jj[it] = j;
+        spp[it] = sp;
+        int off[3] = {0, 0, 0};
+        if (act) child_offsets<LOGN, K>(a, j, sp, off);
+        off1[it] = off[1];
+        const cx<R>* src = wall + t.s * G::SL + t.h * G::HS + t.P * M::WP + pad(NV * (t.m + 1));
+#pragma unroll
+        for (int e = 0; e < NV; ++e) cur[it][0][e] = act ? ldc(src + e) : zero<R>();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const task t = tk[it];
+        if (t.h == 0) rec_levelsT<VA, 0, M::r, 0, MAXL, R>(cur[it], jj[it], spp[it]);
+        else rec_levelsT<VA, 1, M::r, 0, MAXL, R>(cur[it], jj[it], spp[it]);
+        if (t.m < M::GL - 1) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const int hq = t.h ^ (SW ? par(q) : 0);
+                stc(wall + t.s * G::SL + hq * G::HS + (t.P * NV + q) * M::GP + off1[it], cur[it][q][0]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// B0^T for M3 / M7 (the transposed b0_pass_rec: same lane remapping, wave
+// carries of segments longer than a wave through LDS, in the other direction)
+template <int VA, int LOGN, typename R>
+__device__ __forceinline__ void b0T_rec_pass(cx<R>* wall, cx<R>* scr, int tid) {
+    using G = kgeo<LOGN>;
+    constexpr bool SW = variant_traits<VA>::switches;
+    constexpr int LW3 = ilog2c(G::W3);
+    constexpr bool MULTI = G::W3 / 2 > 64;
+    constexpr int MAXL = G::W3 / 2 < 64 ? G::W3 / 2 : 64;
+    const int s = tid / G::T, L = tid - s * G::T;
+    int a = 0, j = 0, sp = 0, p = 0;
+    int off1 = 0;
+    if constexpr (G::NP == 0) {
+        p = L;
+        if (p > 0) {
+            const int e = p - 1;
+            const int b = e < 8 ? 0 : e < 12 ? 1 : e < 14 ? 2 : 3;
+            sp = 8 >> b;
+            j = e - (16 - 2 * sp);
+            a = b;
+            off1 = pad(p);
+        }
+    } else {
+        using M0 = mpass<LOGN, 0>;
+        constexpr int r0 = M0::r, G0 = M0::GL, NS = 1 << r0;
+        if (L < G::W3 - NS) {
+            const int pp = L;
+            p = pp + NS;
+            a = __clz(~(pp << (32 - LW3)));
+            j = pp - (G::W3 - (G::W3 >> a));
+            sp = G::W3 >> (a + 1);
+            off1 = pad(p);
+        } else {
+            p = L - (G::W3 - NS);
+            if (p > 0) {
+                const int e = p - 1;
+                const int b = __clz(~(e << (32 - r0)));
+                sp = (1 << (r0 - 1)) >> b;
+                j = e - ((1 << r0) - 2 * sp);
+                a = LW3 - r0 + b;
+                off1 = 17 * ((e + 1) * (G0 / 16)) + 16;
+            }
+        }
+    }
+    const bool act = p > 0;
+    cx<R> cur[2][8][8];
+    {
+        const int ob = pad(G::H - (G::H >> a) + 8 * j);
+        const cx<R>* ws = wall + s * G::SL;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            cur[0][0][e] = act ? ldc(ws + ob + e) : zero<R>();
+            cur[1][0][e] = act ? ldc(ws + G::HS + ob + e) : zero<R>();
+        }
+    }
+    __syncthreads();
+    const int wl = L & 63;
+    const int wv = L >> 6;
+    const int seg0 = L - j;
+    const bool multi = MULTI && sp > 64;
+    const int pw = multi ? wl : j, nw = multi ? 64 : sp;
+    cx<R>* sc = scr + s * ((G::T / 64) * 8);
+    sfor<0, 3>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        constexpr int NR = 1 << t, n = 1 << (2 - t);  // parent rows of depth t, child entries per lane
+        cx<R> lo[2][NR][n], raw[2][NR][n], loc[2][NR][n], own[2][NR], car[2][NR];
+        sfor<0, 2>([&](auto sc2) {
+            constexpr int side = decltype(sc2)::value;
+            sfor<0, NR>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int sg = side ^ (SW ? par(q) : 0);
+                using RD = rec_dir<VA, sg>;
+                constexpr bool TASC = !RD::asc;
+                cx<R> u[n];
+#pragma unroll
+                for (int e = 0; e < n; ++e) {
+                    lo[side][q][e] = sg == 0 ? cur[side][q][2 * e] : cur[side][q][2 * e + 1];
+                    raw[side][q][e] = sg == 0 ? cur[side][q][2 * e + 1] : cur[side][q][2 * e];
+                    const int i = j * n + e;
+                    u[e] = (RD::alt && (i & 1)) ? cx<R>{-raw[side][q][e].re, -raw[side][q][e].im} : raw[side][q][e];
+                }
+                if constexpr (TASC) {
+                    loc[side][q][0] = u[0];
+#pragma unroll
+                    for (int e = 1; e < n; ++e) loc[side][q][e] = loc[side][q][e - 1] + u[e];
+                    own[side][q] = loc[side][q][n - 1];
+                } else {
+                    loc[side][q][n - 1] = u[n - 1];
+#pragma unroll
+                    for (int e = n - 2; e >= 0; --e) loc[side][q][e] = loc[side][q][e + 1] + u[e];
+                    own[side][q] = loc[side][q][0];
+                }
+                if constexpr (n == 1) pair_excl<TASC, MAXL, R>(u[0], pw, nw, car[side][q], own[side][q]);
+                else car[side][q] = seg_excl<TASC, MAXL, R>(own[side][q], pw, nw);
+            });
+        });
+        if constexpr (MULTI) {
+            sfor<0, 2>([&](auto sc2) {
+                constexpr int side = decltype(sc2)::value;
+                sfor<0, NR>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    constexpr int sg = side ^ (SW ? par(q) : 0);
+                    constexpr bool TASC = !rec_dir<VA, sg>::asc;
+                    if (multi && wl == (TASC ? 63 : 0)) stc(sc + wv * 8 + side * 4 + q, own[side][q] + car[side][q]);
+                });
+            });
+            __syncthreads();
+            if (multi) {
+                const int w0 = seg0 >> 6, w1 = (seg0 + sp - 1) >> 6;
+                sfor<0, 2>([&](auto sc2) {
+                    constexpr int side = decltype(sc2)::value;
+                    sfor<0, NR>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        constexpr int sg = side ^ (SW ? par(q) : 0);
+                        constexpr bool TASC = !rec_dir<VA, sg>::asc;
+                        cx<R> c = zero<R>();
+                        if (TASC) {
+                            for (int w = w0; w < wv; ++w) c = c + ldc(sc + w * 8 + side * 4 + q);
+                        } else {
+                            for (int w = wv + 1; w <= w1; ++w) c = c + ldc(sc + w * 8 + side * 4 + q);
+                        }
+                        car[side][q] = car[side][q] + c;
+                    });
+                });
+            }
+            __syncthreads();
+        }
+        cx<R> nxt[2][8][8];
+        sfor<0, 2>([&](auto sc2) {
+            constexpr int side = decltype(sc2)::value;
+            sfor<0, NR>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int sg = side ^ (SW ? par(q) : 0);
+                using RD = rec_dir<VA, sg>;
+#pragma unroll
+                for (int e = 0; e < n; ++e) {
+                    const int i = j * n + e;
+                    const int len = sp * n;
+                    cx<R> g = (n == 1 ? own[side][q] : loc[side][q][e]) + car[side][q];
+                    if (RD::alt && (i & 1)) g = cx<R>{-g.re, -g.im};
+                    if (len > 1 && (RD::asc ? i == 0 : i == len - 1)) g = g * R(0.5);
+                    nxt[side][2 * q][e] = lo[side][q][e];
+                    nxt[side][2 * q + 1][e] = len == 1 ? raw[side][q][e] : g;
+                }
+            });
+        });
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int q = 0; q < 2 * NR; ++q)
+#pragma unroll
+                for (int e = 0; e < n; ++e) cur[side][q][e] = nxt[side][q][e];
+    });
+    if (act) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int hq = side ^ (SW ? par(q) : 0);
+                stc(wall + s * G::SL + hq * G::HS + q * G::W3P + off1, cur[side][q][0]);
+            }
+    }
+    __syncthreads();
+}
+
 // whole sub-blocks of a row of 2^r slots, transposed rowk: o = the blocks'
 // time values, block-contiguous (block of sz points at 2^r - 2 sz); s[e-1] =
 // slot e receives the spectra (dct_to / dst_to of variant VB)
@@ -695,8 +977,13 @@ __global__ __launch_bounds__(kgeo<LOGN>::WG) void amqft_kB_kernel(const S* __res
     c0T<LOGN, R>(w, raw, m0, conj_in);
     __syncthreads();
     fold<LOGN, R>(wall, tid);
-    b0T_pass<VA, LOGN, R>(wall, tid);
-    sfor<0, G::NP>([&](auto kc) { bT_pass<VA, LOGN, decltype(kc)::value, R>(wall, tid); });
+    if constexpr (variant_traits<VB>::recurrence) {
+        b0T_rec_pass<VA, LOGN, R>(wall, wall + G::SPW * G::SL, tid);
+        sfor<0, G::NP>([&](auto kc) { bT_rec_pass<VA, LOGN, decltype(kc)::value, R>(wall, tid); });
+    } else {
+        b0T_pass<VA, LOGN, R>(wall, tid);
+        sfor<0, G::NP>([&](auto kc) { bT_pass<VA, LOGN, decltype(kc)::value, R>(wall, tid); });
+    }
     p3T_pass<VB, LOGN, R>(wall, kt, tid);
     sfor<0, G::NP>([&](auto kc) { orbitT_pass<VA, VB, LOGN, G::NP - 1 - decltype(kc)::value, R>(wall, kt, kf, tid); });
     if (live) {
@@ -713,7 +1000,7 @@ hipError_t launch_kB_n(const lds_launch& a, hipStream_t st) {
     using G = kgeo<LOGN>;
     const int flags = (a.conj_in ? 1 : 0) | (a.conj_out ? 2 : 0) | (a.onthefly ? 4 : 0);
     const long long grid = (a.batch + G::SPW - 1) / G::SPW;
-    const size_t lds = kA_lds_bytes<R, LOGN>();
+    const size_t lds = kA_lds_bytes_v<transposed_of<VB>::V, R, LOGN>();
     hipLaunchKernelGGL((amqft_kB_kernel<VB, S, LOGN>), dim3((unsigned)grid), dim3(G::WG), lds, st,
                        static_cast<const S*>(a.in), static_cast<S*>(a.out), static_cast<const R*>(a.ktab),
                        (long long)a.batch, a.ktab_log2n - LOGN, flags, static_cast<const long long*>(a.offsets));
@@ -769,7 +1056,7 @@ hipError_t prime_kB_v(int dtype) {
 }  // namespace
 
 bool kB_supported(int variant, int logn, int dtype) {
-    if (variant != 2 && variant != 6) return false;
+    if (variant != 2 && variant != 3 && variant != 6 && variant != 7) return false;
     if (dtype == 0) return logn >= 8 && logn <= 13;
     return logn >= 8 && logn <= 14;
 }
@@ -777,13 +1064,22 @@ bool kB_supported(int variant, int logn, int dtype) {
 hipError_t launch_kB(const lds_launch& a, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
     if (!kB_supported(a.variant, a.logn, a.dtype)) return hipErrorInvalidValue;
-    return a.variant == 2 ? launch_kB_v<2>(a, st) : launch_kB_v<6>(a, st);
+    switch (a.variant) {
+    case 2: return launch_kB_v<2>(a, st);
+    case 3: return launch_kB_v<3>(a, st);
+    case 6: return launch_kB_v<6>(a, st);
+    default: return launch_kB_v<7>(a, st);
+    }
 }
 
 hipError_t prime_kB(int variant, int dtype) {
-    if (variant == 2) return prime_kB_v<2>(dtype);
-    if (variant == 6) return prime_kB_v<6>(dtype);
-    return hipSuccess;
+    switch (variant) {
+    case 2: return prime_kB_v<2>(dtype);
+    case 3: return prime_kB_v<3>(dtype);
+    case 6: return prime_kB_v<6>(dtype);
+    case 7: return prime_kB_v<7>(dtype);
+    default: return hipSuccess;
+    }
 }
 
 }  // namespace amqft

@@ -598,7 +598,8 @@ void describe_lds(const lds_launch& a, char* buf, size_t len) {
         snprintf(buf, len, "amqft_kA_kernel<%d, %s, %d> grid=%lld block=%d lds=%zu", a.variant, sname, a.logn,
                  (long long)((a.batch + spw - 1) / spw), threads, lds);
     } else if (!a.generic && kB_supported(a.variant, a.logn, a.dtype)) {
-        kA_shape(a.logn, a.dtype, &threads, &spw, &lds);  // the same geometry and LDS as the skeleton-A kernel
+        kA_shape(a.logn, a.dtype, &threads, &spw, &lds);  // the geometry and LDS of its skeleton-A transpose
+        lds = kA_lds(a.variant == 2 ? 4 : a.variant == 6 ? 8 : a.variant == 3 ? 1 : 5, a.logn, a.dtype);
         snprintf(buf, len, "amqft_kB_kernel<%d, %s, %d> grid=%lld block=%d lds=%zu", a.variant, sname, a.logn,
                  (long long)((a.batch + spw - 1) / spw), threads, lds);
     } else if (!a.generic && fast_supported(a.logn, a.dtype)) {

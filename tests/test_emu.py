@@ -41,6 +41,9 @@ CASES = [
     ("tkernel", 6, 0, 10, 2, 0),
     ("tkernel", 6, 1, 8, 3, 1),
     ("tkernel", 2, 1, 14, 1, 1),
+    ("tkernel", 3, 0, 8, 5, 0),  # transposed recurrences, four signals per workgroup
+    ("tkernel", 3, 1, 14, 1, 0),  # ... across several waves
+    ("tkernel", 7, 0, 12, 1, 1),
     ("large", 4, 0, 11, 2, 0),   # top / rows / back / bchain, rows sharing workgroups
     ("large", 8, 0, 12, 1, 1),
     ("generic", 3, 0, 10, 3, 0),  # level engine
