@@ -81,7 +81,18 @@ enum {
      * LDS: from N = 2^11, FP64 and FP32 storage only (AMQFT_ERR_UNSUPPORTED
      * otherwise, and together with AMQFT_FLAG_FORCE_MULTIPASS).  For tests of
      * that path at sizes where every variant is accurate. */
-    AMQFT_FLAG_FORCE_LARGE = 8u
+    AMQFT_FLAG_FORCE_LARGE = 8u,
+    /* amqft_exec_adjoint runs the transposed flow graph of the plan's
+     * variant instead of conjugating around its forward program.  The real
+     * transpose of a program for F computes F^H (F is symmetric,
+     * eq. qft_0A), and the transpose of variant 4's program is variant 2's
+     * with the sign of i in the combine flipped (M4^T = M2, M8^T = M6,
+     * M1^T = M3, M5^T = M7; skeleton A <-> B, Sec. 5-6), so the adjoint of a
+     * variant-v plan runs the compile-time kernel of its dual variant.  For
+     * N = 2^8 .. 2^14 (2^13 in FP64), where both kernels exist
+     * (AMQFT_ERR_UNSUPPORTED otherwise and for many-length plans); the
+     * forward transform is unchanged. */
+    AMQFT_FLAG_TRANSPOSED_ADJOINT = 16u
 };
 
 /* Environment (read at plan creation):

@@ -19,6 +19,7 @@ FLAG_ONTHEFLY_CONSTANTS = 1
 FLAG_NO_AUTOTUNE = 2
 FLAG_FORCE_MULTIPASS = 4
 FLAG_FORCE_LARGE = 8
+FLAG_TRANSPOSED_ADJOINT = 16
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 #: every function the header declares, with its ctypes signature

@@ -91,7 +91,19 @@ amqft_status hip_fail(hipError_t e) {
 bool valid_variant(int v) { return v >= 1 && v <= 8; }
 bool valid_dtype(int t) { return t >= 0 && t <= 3; }
 constexpr unsigned kAllFlags = AMQFT_FLAG_ONTHEFLY_CONSTANTS | AMQFT_FLAG_NO_AUTOTUNE | AMQFT_FLAG_FORCE_MULTIPASS |
-                               AMQFT_FLAG_FORCE_LARGE;
+                               AMQFT_FLAG_FORCE_LARGE | AMQFT_FLAG_TRANSPOSED_ADJOINT;
+
+// the variant whose program is the transpose of variant v's (skeleton A <-> B)
+int dual_variant(int v) {
+    static const int d[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    return d[v];
+}
+
+// both compile-time kernels exist for v and its dual at this size
+bool transposed_adjoint_supported(int v, int logn, int dtype) {
+    const int a = (v == 1 || v == 4 || v == 5 || v == 8) ? v : dual_variant(v);
+    return kA_supported(a, logn, dtype) && kB_supported(dual_variant(a), logn, dtype);
+}
 constexpr unsigned kForceFlags = AMQFT_FLAG_FORCE_MULTIPASS | AMQFT_FLAG_FORCE_LARGE;
 
 int log2_exact(int64_t n) {
@@ -264,7 +276,9 @@ amqft_status exec_single(amqft_plan p, const void* in, void* out, hipStream_t st
         return e == hipSuccess ? AMQFT_OK : hip_fail(e);
     }
     lds_launch a{};
-    a.variant = p->variant;
+    // the transposed flow graph of variant v: its dual variant's program with
+    // the sign of i flipped, i.e. conjugated on load and store
+    a.variant = adjoint && (p->flags & AMQFT_FLAG_TRANSPOSED_ADJOINT) ? dual_variant(p->variant) : p->variant;
     a.dtype = p->dtype;
     a.logn = p->logn;
     a.batch = p->batch;
@@ -525,6 +539,9 @@ amqft_status amqft_plan_create(amqft_plan* out, int64_t n, int64_t batch, amqft_
     if (logn < 0) return AMQFT_ERR_NOT_POW2;
     if (logn > AMQFT_MAX_LOG2N) return AMQFT_ERR_UNSUPPORTED;
     if ((flags & kForceFlags) == kForceFlags) return AMQFT_ERR_UNSUPPORTED;
+    if ((flags & AMQFT_FLAG_TRANSPOSED_ADJOINT) &&
+        ((flags & kForceFlags) || !transposed_adjoint_supported((int)variant, logn, (int)dtype)))
+        return AMQFT_ERR_UNSUPPORTED;
     if ((flags & AMQFT_FLAG_FORCE_LARGE) && !kL_supported_forced((int)variant, logn, (int)dtype))
         return AMQFT_ERR_UNSUPPORTED;
     const bool mp = logn > max_lds_log2((int)dtype) || (flags & kForceFlags);
@@ -542,7 +559,7 @@ amqft_status amqft_plan_create_real(amqft_plan* out, int64_t n, int64_t batch, a
     if (flags & ~kAllFlags) return AMQFT_ERR_INVALID_ARG;
     const int logn = log2_exact(n);
     if (logn < 0) return AMQFT_ERR_NOT_POW2;
-    if (flags & kForceFlags) return AMQFT_ERR_UNSUPPORTED;
+    if (flags & (kForceFlags | AMQFT_FLAG_TRANSPOSED_ADJOINT)) return AMQFT_ERR_UNSUPPORTED;
     if (dtype != AMQFT_C128 && dtype != AMQFT_C64) return AMQFT_ERR_UNSUPPORTED;
     if (logn < 2 || logn > max_lds_log2((int)dtype)) return AMQFT_ERR_UNSUPPORTED;
     if (batch > (int64_t(1) << 40)) return AMQFT_ERR_UNSUPPORTED;
@@ -572,6 +589,7 @@ amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_
     if (!valid_variant((int)variant) || !valid_dtype((int)dtype) || count < 0) return AMQFT_ERR_INVALID_ARG;
     if (count > 0 && (!lengths_host || !offsets_host)) return AMQFT_ERR_INVALID_ARG;
     if (flags & ~kAllFlags) return AMQFT_ERR_INVALID_ARG;
+    if (flags & AMQFT_FLAG_TRANSPOSED_ADJOINT) return AMQFT_ERR_UNSUPPORTED;
     int maxlog = 2;
     for (int64_t i = 0; i < count; ++i) {
         const int l = log2_exact(lengths_host[i]);

@@ -23,7 +23,8 @@ KERNELS = ["amqft_kA.hip", "amqft_lds.hip", "amqft_fast.hip", "amqft_kB.hip"]
 HEADERS = ["amqft_device.h", "amqft_internal.h", "amqft_levels.h", "amqft_leaf.h", "amqft_kA_passes.h"]
 CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 SMEM = re.compile(r"extern\s+__shared__\s+__align__\(\d+\)\s+unsigned\s+char\s+smem\[\];")
-FLAGS = ["-std=c++20", "-O0", "-gline-tables-only", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+FLAGS = ["-std=c++20", "-O0", "-gline-tables-only", "-ffp-contract=off", "-fno-omit-frame-pointer",
+         "-fsanitize=address,undefined",
          "-fno-sanitize-recover=undefined", "-Wno-unused-value", "-Wno-ignored-attributes", "-pthread"]
 
 

@@ -137,3 +137,22 @@ def test_create_real_validation(lib, args, status):
     h = ctypes.c_void_p(5)
     assert lib.amqft_plan_create_real(ctypes.byref(h), *args) == status
     assert not h.value
+
+
+@pytest.mark.parametrize("n,variant,dtype", [(64, 4, 1), (1 << 15, 4, 1), (1 << 14, 2, 0), (128, 6, 0)])
+def test_transposed_adjoint_validation(lib, n, variant, dtype):
+    """The transposed-flow-graph adjoint exists where both compile-time kernels
+    do (2^8 .. 2^14, FP64 to 2^13); elsewhere plan creation refuses it before
+    any HIP call."""
+    rc, h = _create(lib, n, variant=variant, dtype=dtype, flags=16)
+    assert rc == _lib.ERR_UNSUPPORTED
+    assert not h.value
+
+
+def test_transposed_adjoint_not_for_many_or_real(lib):
+    import numpy as np
+    h = ctypes.c_void_p(3)
+    L = np.array([256, 256], dtype=np.int64)
+    O = np.array([0, 256, 512], dtype=np.int64)
+    assert lib.amqft_plan_create_many(ctypes.byref(h), 2, L.ctypes.data, O.ctypes.data, 4, 1, 16) == _lib.ERR_UNSUPPORTED
+    assert lib.amqft_plan_create_real(ctypes.byref(h), 256, 1, 0, 4, 1, 16) == _lib.ERR_UNSUPPORTED

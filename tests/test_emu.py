@@ -69,3 +69,26 @@ def test_kernel_source_on_cpu(emu_exe, tmp_path, path, variant, dtype, logn, bat
     b = bound(variant, dtype == 0, src, ref if not conj else np.conj(ref))
     assert b is not None, "every emulated case is chosen where its variant has a pin"
     assert rel(y, ref) <= b, (rel(y, ref), b)
+
+
+@pytest.mark.parametrize("vb,logn", [(2, 12), (6, 9), (2, 8), (6, 8)])
+def test_transposed_program_is_the_dual_variant(emu_exe, tmp_path, vb, logn):
+    """The duality of the paper's M steps (M4^T = M2, M8^T = M6; skeleton A
+    <-> B): the transposed program of the skeleton-A kernel of variant 4 (8),
+    run without FMA contraction, reproduces the oracle's FP32 build of
+    variant 2 (6) bit for bit -- including variant 6's ill-conditioned
+    rounding, which differs from variant 8's by more than the error itself."""
+    import oracle
+    n, batch = 1 << logn, 3
+    x = inputs.complex_normal(31 + logn, batch, n).astype(np.complex64)
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    x.tofile(fin)
+    r = subprocess.run([emu_exe, "tkernel", str(vb), "1", str(logn), str(batch), "0", fin, fout],
+                       capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1"))
+    assert r.returncode == 0, r.stderr[-4000:]
+    y = np.fromfile(fout, dtype=np.complex64).reshape(batch, n)
+    emu = oracle.cdft(x, vb, prec="f32")
+    assert np.array_equal(y, emu), rel(y, emu)
+    if vb == 6:  # the skeleton-A twin rounds differently
+        assert not np.array_equal(y, oracle.cdft(x, 8, prec="f32"))

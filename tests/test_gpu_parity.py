@@ -147,6 +147,49 @@ def test_fp64_repeated_launches_identical(n):
     assert e <= 1e-12, (n, e)
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_transposed_graph_adjoint(variant):
+    """F^H by the transposed flow graph (AMQFT_FLAG_TRANSPOSED_ADJOINT): the
+    real transpose of variant v's program, which is the program of its dual
+    variant (M4^T = M2, M8^T = M6, M1^T = M3, M5^T = M7) with the sign of i
+    flipped.  Against the oracle's F^H (pinned by the dual variant's own
+    error, since that is the arithmetic performed); bit for bit against the
+    conjugation-fused adjoint of the dual variant (the same program); its
+    rounding compared with the conjugation-fused adjoint of variant v; the
+    forward transform of the plan unchanged."""
+    api = _api()
+    from paper_1404_1810_amd import _lib
+    dual = {1: 3, 2: 4, 3: 1, 4: 2, 5: 7, 6: 8, 7: 5, 8: 6}[variant]
+    reports = []
+    for dtype, n, batch in (("c128", 256, 5), ("c128", 4096, 2), ("c64", 4096, 3), ("c64", 16384, 2)):
+        f64 = dtype == "c128"
+        code = _lib.C128 if f64 else _lib.C64
+        g_np = inputs.complex_normal(88 + n, batch, n)
+        if not f64:
+            g_np = g_np.astype(np.complex64)
+        _say("transposed-graph adjoint variant", variant, dtype, "n", n)
+        ref = np.conj(truth(np.conj(g_np), 4))
+        g = torch.from_numpy(g_np).cuda()
+        pt = api.Plan(n, batch, variant, code, _lib.FLAG_TRANSPOSED_ADJOINT)
+        pc = api.Plan(n, batch, variant, code, 0)
+        pd = api.Plan(n, batch, dual, code, 0)
+        yt = pt.exec(g, adjoint=True)
+        yc = pc.exec(g, adjoint=True)
+        yd = pd.exec(g, adjoint=True)
+        ft, fc = pt.exec(g), pc.exec(g)
+        torch.cuda.synchronize()
+        assert "amqft_k" in pt.describe()
+        assert torch.equal(ft, fc)
+        assert torch.equal(yt, yd)
+        yt_np = yt.cpu().numpy()
+        _say("  rel to oracle %.3e, to the conjugation-fused adjoint %.3e" % (rel(yt_np, ref), rel(yt_np, yc.cpu().numpy())))
+        reports.append(assess(np.conj(yt_np), np.conj(ref), dual, f64, np.conj(g_np), "%s n=%d" % (dtype, n)))
+        for p in (pt, pc, pd):
+            p.close()
+    xfail_unpinned(reports)
+
+
 MP_FORCED = (("c64", 32), ("c64", 128), ("c64", 1024), ("c64", 4096), ("c128", 256), ("c128", 1024), ("c128", 2048))
 
 
