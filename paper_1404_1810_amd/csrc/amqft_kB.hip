@@ -116,8 +116,8 @@ __device__ __forceinline__ void combineT_run(const cx<R>* P, cx<R>* L, cx<R>* Hh
 }
 
 // r transposed levels below a parent of context SGB on a window of W runs
-// of 2^r parent values (run w = child index j - W/2 + w): cur[0] holds the
-// W 2^r parent values; out[q] = child q's value at the middle run
+// of 2^r parent values: cur[0] holds the W 2^r parent values; after the
+// levels, cur[q][w] = child q's value at run w of the window
 template <int V, int SGB, int r, int t, int W, typename R>
 __device__ __forceinline__ void fwd_levelsT(cx<R> (&cur)[1 << r][W << r]) {
     if constexpr (t < r) {
@@ -141,6 +141,18 @@ __device__ __forceinline__ void fwd_levelsT(cx<R> (&cur)[1 << r][W << r]) {
         fwd_levelsT<V, SGB, r, t + 1, W, R>(cur);
     }
 }
+
+// The window a child index needs: its own run and the runs whose parent
+// values reach it through the time-side M2 / M6 terms.  M2 (from M4) in DCT
+// context takes the neighbour before (H'[i] = P'[2i+1] + P'[2i-1]), in DST
+// context the one after; M6 (from M8) switches context from row to row, so
+// both.  OFF = first run relative to the child index, W = runs.
+template <int VA, int SGB>
+struct halo_window {
+    static constexpr bool both = variant_traits<VA>::switches;
+    static constexpr int W = both ? 3 : 2;
+    static constexpr int OFF = both ? -1 : (SGB == 0 ? -1 : 0);
+};
 
 // ---------------------------------------------------------------------------
 // C0^T: one thread per orbit of 16 outputs' positions (the F1 orbit); every
@@ -337,33 +349,37 @@ __device__ __forceinline__ void b0T_pass(cx<R>* wall, int tid) {
         }
     }
     const bool act = p > 0;
-    cx<R> cur[2][8][24];
+    using W0 = halo_window<VA, 0>;
+    using W1 = halo_window<VA, 1>;
+    cx<R> cur0[8][W0::W * 8], cur1[8][W1::W * 8];
     if (act) {
         cx<R>* ws = wall + s * G::SL;
+        auto load = [&](auto& cur, auto wc, int side) {
+            using WW = decltype(wc);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int jj = j - 1 + d;
-            const bool in = jj >= 0 && jj < sp;
-            const int ob = pad(G::H - (G::H >> a) + 8 * (in ? jj : 0));
+            for (int d = 0; d < WW::W; ++d) {
+                const int jj = j + WW::OFF + d;
+                const bool in = jj >= 0 && jj < sp;
+                const int ob = pad(G::H - (G::H >> a) + 8 * (in ? jj : j));
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const cx<R> v0 = ldc(ws + ob + e), v1 = ldc(ws + G::HS + ob + e);
-                cur[0][0][8 * d + e] = in ? v0 : zero<R>();
-                cur[1][0][8 * d + e] = in ? v1 : zero<R>();
+                for (int e = 0; e < 8; ++e) {
+                    const cx<R> v = ldc(ws + side * G::HS + ob + e);
+                    cur[0][8 * d + e] = in ? v : zero<R>();
+                }
             }
-        }
+        };
+        load(cur0, W0{}, 0);
+        load(cur1, W1{}, 1);
     }
     __syncthreads();
     if (act) {
-        fwd_levelsT<VA, 0, 3, 0, 3, R>(cur[0]);
-        fwd_levelsT<VA, 1, 3, 0, 3, R>(cur[1]);
+        fwd_levelsT<VA, 0, 3, 0, W0::W, R>(cur0);
+        fwd_levelsT<VA, 1, 3, 0, W1::W, R>(cur1);
 #pragma unroll
-        for (int side = 0; side < 2; ++side)
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int hq = side ^ (SW ? par(q) : 0);
-                stc(wall + s * G::SL + hq * G::HS + q * G::W3P + off1, cur[side][q][1]);
-            }
+        for (int q = 0; q < 8; ++q) {
+            stc(wall + s * G::SL + (0 ^ (SW ? par(q) : 0)) * G::HS + q * G::W3P + off1, cur0[q][-W0::OFF]);
+            stc(wall + s * G::SL + (1 ^ (SW ? par(q) : 0)) * G::HS + q * G::W3P + off1, cur1[q][-W1::OFF]);
+        }
     }
     __syncthreads();
 }
@@ -377,7 +393,10 @@ __device__ __forceinline__ void bT_pass(cx<R>* wall, int tid) {
     using M = mpass<LOGN, K>;
     constexpr bool SW = variant_traits<VA>::switches;
     constexpr int NV = M::NV, IT = M::IT, LG = ilog2c(M::GL);
-    cx<R> cur[IT][NV][3 * NV];
+    // one window shape for both halves: a wave's tasks share a half, but the
+    // compile-time window must cover both contexts
+    constexpr int W = variant_traits<VA>::switches ? 3 : 2;
+    cx<R> cur[IT][NV][W * NV];
     int off1[IT];
     task tk[IT];
 #pragma unroll
@@ -394,11 +413,14 @@ __device__ __forceinline__ void bT_pass(cx<R>* wall, int tid) {
             child_offsets<LOGN, K>(a, j, sp, off);
             off1[it] = off[1];
             const cx<R>* src = wall + t.s * G::SL + t.h * G::HS + t.P * M::WP;
+            // first run of the window relative to j: -1 (both neighbours, or
+            // the one before in DCT context) or 0 (the one after, DST context)
+            const int woff = W == 3 ? -1 : (t.h == 0 ? -1 : 0);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int jj = j - 1 + d;
+            for (int d = 0; d < W; ++d) {
+                const int jj = j + woff + d;
                 const bool in = jj >= 0 && jj < sp;
-                const int base = pad(NV * (in ? t.m - 1 + d : t.m));
+                const int base = pad(NV * (in ? t.m + woff + d : t.m));
 #pragma unroll
                 for (int e = 0; e < NV; ++e) {
                     const cx<R> v = ldc(src + base + e);
@@ -412,12 +434,13 @@ __device__ __forceinline__ void bT_pass(cx<R>* wall, int tid) {
     for (int it = 0; it < IT; ++it) {
         const task t = tk[it];
         if (t.m > 0) {
-            if (t.h == 0) fwd_levelsT<VA, 0, M::r, 0, 3, R>(cur[it]);
-            else fwd_levelsT<VA, 1, M::r, 0, 3, R>(cur[it]);
+            const int own = W == 3 ? 1 : (t.h == 0 ? 1 : 0);  // the child index's own run in the window
+            if (t.h == 0) fwd_levelsT<VA, 0, M::r, 0, W, R>(cur[it]);
+            else fwd_levelsT<VA, 1, M::r, 0, W, R>(cur[it]);
 #pragma unroll
             for (int q = 0; q < NV; ++q) {
                 const int hq = t.h ^ (SW ? par(q) : 0);
-                stc(wall + t.s * G::SL + hq * G::HS + (t.P * NV + q) * M::GP + off1[it], cur[it][q][1]);
+                stc(wall + t.s * G::SL + hq * G::HS + (t.P * NV + q) * M::GP + off1[it], own ? cur[it][q][1] : cur[it][q][0]);
             }
         }
     }
