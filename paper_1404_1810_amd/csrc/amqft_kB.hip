@@ -22,9 +22,9 @@
 //          of the combine, the three top levels of the chain's D_k^T: blocks
 //          0..2 of both sides into the depth-0 block layout, the level-3 chain
 //          values into the places of blocks 3.. (FOLD's input).
-//   FOLD   the chain's D_k^T for levels 3 .. D-3, one level per barrier
-//          (each thread takes the pairs k and q - k, in place): blocks 3..D-3
-//          and the values of dct[16] / dst[16] (the chain slots).
+//   FOLD   the chain's D_k^T for levels 3 .. D-3, one lane per orbit of
+//          positions that the reflections keep together, in registers:
+//          blocks 3..D-3 and the values of dct[16] / dst[16] (the chain slots).
 //   B0^T   levels 0..2 of dct_to / dst_to: time splits with the M2 / M6
 //          neighbour sums (the transposed B0: the +-1 neighbours of a child
 //          index come from the neighbouring threads' runs, read as a window).
@@ -248,65 +248,118 @@ __device__ __forceinline__ void c0T(cx<R>* w, const cx<R> (&raw)[16], int k0, bo
 // ---------------------------------------------------------------------------
 // FOLD: D_k^T of the chain for levels a = 3 .. D-3 (C0 walked these levels
 // along each harmonic's reflection path; here they are summed level by
-// level).  Per level, thread k takes the pairs of k and q - k; the last level
-// writes the dct[16] / dst[16] values into the chain slots.
+// level).  A level of length L = 2 q_a folds E(k) with E(L - k) into the
+// block entry E(k) - E(L - k) (k < q_a) and the next level's E(k) + E(L - k),
+// E(q_a) becoming the next top; the DST side S(k) with S(L - k) into
+// S(k) + S(L - k) and S(k) - S(L - k), S(q_a) staying a block entry.  The
+// positions congruent to +-r modulo a power of two P stay among themselves
+// under every fold down to L = P, so one lane takes each such orbit and walks
+// those levels in registers with no barrier, storing its block entries as it
+// goes and, after L = P, its values of the level L = P / 2.  The tail
+// (L = P / 2 .. 16) is the same walk with P = 16 after a wave barrier: every
+// orbit lane of a signal is a lane of the signal's first wave.  The last
+// level writes the dct[16] / dst[16] values into the chain slots.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// orbit modulus of the first walk: at most 16 complex values a lane up to
+// N = 2^13 (32 at 2^14), at most 64 lanes a signal
+template <int LOGN>
+constexpr int fold_p1() {
+    constexpr int p = (1 << LOGN) / 128;
+    return p < 16 ? 16 : p > 64 ? 64 : p;
+}
+
+// One walk on a side (DST: S values, else E values) from the level of length
+// LS down to L = P, lane orbit r (0 = the orbit of the multiples of P / 2).
+// The level of length L holds E(k) at H - L + k (k < L) with the top E(L) in
+// chain slot 8, and S(k) at H - L + k - 1 (0 < k < L).  The lane's values v[i]
+// of a level of length L = MP sit at k(i) = P floor(i / 2) + (i odd ? P - r :
+// r) (orbit 0: k(i) = i P / 2, v[2M] the top); the fold pairs v[i] (i < M)
+// with v[2M - 1 - i] (orbit 0: v[2M - i]), so every lane runs the same code
+// (no divergence) and the values stay in registers.
+template <int LOGN, int P, int LS, typename R>
+struct fold_walk {
+    using G = kgeo<LOGN>;
+    using L = lds_layout<LOGN>;
+    static constexpr int M0 = LS / P;
+    static constexpr int NV = 2 * M0 + 1;
+    static constexpr int NL = ilog2c(M0) + 1;  // levels LS, LS / 2, .., P
+    static constexpr bool LAST = P == 16;
+
+    template <int Lv>
+    static __device__ __forceinline__ int pos(bool dst, int k) {
+        return hslot<LOGN>(dst, G::H - Lv + k - (dst ? 1 : 0));
+    }
+    static __device__ __forceinline__ int kpos(int i, int r) {
+        return P * (i >> 1) + ((i & 1) ? (r > 0 ? P - r : P / 2) : r);
+    }
+
+    // the orbit's values of the level LS; slots a lane's orbit lacks (S(0),
+    // and v[2 M0] outside the DCT orbit 0) read a position of its own orbit
+    static __device__ __forceinline__ void load(const cx<R>* w, bool dst, int r, cx<R> (&v)[NV]) {
+#pragma unroll
+        for (int i = 0; i < 2 * M0; ++i) v[i] = ldc(w + pos<LS>(dst, kpos(i, r) + (dst && i == 0 && r == 0 ? P / 2 : 0)));
+        v[2 * M0] = ldc(w + (!dst && r == 0 ? L::chain(8) : pos<LS>(dst, kpos(1, r))));
+    }
+
+    static __device__ __forceinline__ void walk(cx<R>* w, bool dst, int r, cx<R> (&v)[NV]) {
+        const bool o0 = r == 0;
+        sfor<0, NL>([&](auto lc) {
+            constexpr int Lv = LS >> decltype(lc)::value;
+            constexpr int M = Lv / P;
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const cx<R> b = o0 ? v[2 * M - i] : v[2 * M - 1 - i];
+                const cx<R> sb = dst ? cx<R>{-b.re, -b.im} : b;  // DCT: E -+ E', DST: S +- S'
+                if (!(dst && o0 && i == 0)) stc(w + pos<Lv>(dst, kpos(i, r)), v[i] - sb);
+                v[i] = v[i] + sb;
+            }
+            // orbit 0: E(L / 2) = v[M] becomes the next top; S(L / 2) stays a
+            // block entry (in place on the first level)
+            if constexpr (Lv != LS) {
+                if (dst && o0) stc(w + pos<Lv>(true, Lv / 2), v[M]);
+            }
+        });
+        // v[0]: index r of the level P / 2 (none for the DST orbit 0)
+        const int o = LAST ? L::chain((dst ? 8 : 0) + r) : pos<P / 2>(dst, r);
+        if (!(dst && o0)) stc(w + o, v[0]);
+        if (!dst && o0) stc(w + L::chain(8), v[1]);
+    }
+};
+
 template <int LOGN, typename R>
 __device__ __forceinline__ void fold(cx<R>* wall, int tid) {
     using G = kgeo<LOGN>;
-    using L = lds_layout<LOGN>;
-    constexpr int H = G::H, D = G::D;
+    constexpr int P1 = fold_p1<LOGN>(), L0 = G::N / 16;
+    static_assert(P1 <= 64 && P1 <= G::T, "a signal's orbit lanes must fit its first wave");
     const int s = tid / G::T, k = tid - s * G::T;
     cx<R>* w = wall + s * G::SL;
-    sfor<3, D - 2>([&](auto ac) {
-        constexpr int a = decltype(ac)::value;
-        constexpr int q = G::N >> (a + 2);
-        constexpr bool last = a == D - 3;
-        constexpr int E0 = H - 2 * q;  // E(k) at E0 + k
-        if (k <= q / 2) {
-            // DCT side
-            auto putE = [&](int i, cx<R> v) {  // E_{a+1}(i), i < q
-                if (last) stc(w + L::chain(i), v);
-                else stc(w + hslot<LOGN>(0, H - q + i), v);
-            };
-            if (k == 0) {
-                const cx<R> e0 = ldc(w + hslot<LOGN>(0, E0)), top = ldc(w + L::chain(8));
-                const cx<R> eq = ldc(w + hslot<LOGN>(0, H - q));
-                stc(w + hslot<LOGN>(0, E0), e0 - top);
-                putE(0, e0 + top);
-                stc(w + L::chain(8), eq);
-            } else if (k < q / 2) {
-                const cx<R> xa = ldc(w + hslot<LOGN>(0, E0 + k)), xb = ldc(w + hslot<LOGN>(0, H - k));
-                const cx<R> xc = ldc(w + hslot<LOGN>(0, H - q - k)), xd = ldc(w + hslot<LOGN>(0, H - q + k));
-                stc(w + hslot<LOGN>(0, E0 + k), xa - xb);
-                putE(k, xa + xb);
-                stc(w + hslot<LOGN>(0, H - q - k), xc - xd);
-                putE(q - k, xc + xd);
-            } else {
-                const cx<R> xa = ldc(w + hslot<LOGN>(0, E0 + k)), xb = ldc(w + hslot<LOGN>(0, H - k));
-                stc(w + hslot<LOGN>(0, E0 + k), xa - xb);
-                putE(k, xa + xb);
-            }
-            // DST side: S(k) at E0 + k - 1
-            auto putS = [&](int i, cx<R> v) {  // S_{a+1}(i), i = 1 .. q-1
-                if (last) stc(w + L::chain(8 + i), v);
-                else stc(w + hslot<LOGN>(1, H - q + i - 1), v);
-            };
-            if (k >= 1 && k < q / 2) {
-                const cx<R> xa = ldc(w + hslot<LOGN>(1, E0 + k - 1)), xb = ldc(w + hslot<LOGN>(1, H - k - 1));
-                const cx<R> xc = ldc(w + hslot<LOGN>(1, H - q - k - 1)), xd = ldc(w + hslot<LOGN>(1, H - q + k - 1));
-                stc(w + hslot<LOGN>(1, E0 + k - 1), xa + xb);
-                putS(k, xa - xb);
-                stc(w + hslot<LOGN>(1, H - q - k - 1), xc + xd);
-                putS(q - k, xc - xd);
-            } else if (k == q / 2) {
-                const cx<R> xa = ldc(w + hslot<LOGN>(1, E0 + k - 1)), xb = ldc(w + hslot<LOGN>(1, H - k - 1));
-                stc(w + hslot<LOGN>(1, E0 + k - 1), xa + xb);
-                putS(k, xa - xb);
-            }
-        }
-        __syncthreads();
-    });
+    {
+        using F = fold_walk<LOGN, P1, L0, R>;
+        const bool act = k < P1, dst = k >= P1 / 2;
+        const int r = k & (P1 / 2 - 1);
+        cx<R> v[F::NV];
+        if (act) F::load(w, dst, r, v);
+        // the values of the level P1 / 2 land where other lanes' loads were
+        // (the last level writes only chain slots and the lane's own orbit)
+        if constexpr (!F::LAST) wave_sync();
+        if (act) F::walk(w, dst, r, v);
+    }
+    if constexpr (P1 > 16) {
+        using F = fold_walk<LOGN, 16, P1 / 2, R>;
+        wave_sync();
+        const bool act = k < 16, dst = k >= 8;
+        const int r = k & 7;
+        cx<R> v[F::NV];
+        if (act) F::load(w, dst, r, v);
+        if (act) F::walk(w, dst, r, v);
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -434,14 +487,21 @@ __device__ __forceinline__ void bT_pass(cx<R>* wall, int tid) {
     for (int it = 0; it < IT; ++it) {
         const task t = tk[it];
         if (t.m > 0) {
-            const int own = W == 3 ? 1 : (t.h == 0 ? 1 : 0);  // the child index's own run in the window
-            if (t.h == 0) fwd_levelsT<VA, 0, M::r, 0, W, R>(cur[it]);
-            else fwd_levelsT<VA, 1, M::r, 0, W, R>(cur[it]);
+            // the half fixes the context of the levels and, for a window of
+            // two runs, which of them is the child index's own (a compile-time
+            // index keeps the window in registers)
+            auto finish = [&](auto hc) {
+                constexpr int h = decltype(hc)::value;
+                constexpr int own = W == 3 ? 1 : (h == 0 ? 1 : 0);
+                fwd_levelsT<VA, h, M::r, 0, W, R>(cur[it]);
 #pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const int hq = t.h ^ (SW ? par(q) : 0);
-                stc(wall + t.s * G::SL + hq * G::HS + (t.P * NV + q) * M::GP + off1[it], own ? cur[it][q][1] : cur[it][q][0]);
-            }
+                for (int q = 0; q < NV; ++q) {
+                    const int hq = h ^ (SW ? par(q) : 0);
+                    stc(wall + t.s * G::SL + hq * G::HS + (t.P * NV + q) * M::GP + off1[it], cur[it][q][own]);
+                }
+            };
+            if (t.h == 0) finish(std::integral_constant<int, 0>{});
+            else finish(std::integral_constant<int, 1>{});
         }
     }
     __syncthreads();

@@ -54,7 +54,7 @@ namespace emu {
 // barrier epoch); a write after another thread's read or write, or a read
 // after another thread's write, in the same epoch is a race.
 struct word_state {
-    int w_epoch = -1, w_thread = -1, r_epoch = -1, r_thread = -1;
+    int w_epoch = -1, w_thread = -1, w_wepoch = -1, r_epoch = -1, r_thread = -1, r_wepoch = -1;
 };
 
 struct epoch_tick {
@@ -78,6 +78,7 @@ inline std::atomic<long> g_races{0};
 inline void epoch_tick::operator()() noexcept { ++g_block->epoch; }
 inline thread_local emu_uint3 t_threadIdx{0, 0, 0}, t_blockIdx{0, 0, 0};
 inline thread_local dim3 t_blockDim{1, 1, 1}, t_gridDim{1, 1, 1};
+inline thread_local int t_wave_epoch = 0;  // wave barriers this thread has passed
 
 inline unsigned char* lds_base() { return g_block->lds; }
 
@@ -86,28 +87,39 @@ inline void lds_touch(const void* p, size_t bytes, bool write) {
     if (!b || !b->lds) return;
     const unsigned char* c = static_cast<const unsigned char*>(p);
     if (c < b->lds || c >= b->lds + b->lds_bytes) return;  // not LDS
-    const int t = (int)t_threadIdx.x;
+    const int t = (int)t_threadIdx.x, we = t_wave_epoch;
+    // two accesses by lanes of one wave on either side of a wave barrier are ordered
+    auto ordered = [&](int other, int other_we) {
+        return other >= 0 && (other >> 6) == (t >> 6) && other_we != we;
+    };
     std::lock_guard<std::mutex> g(b->mu);
     for (size_t w = (size_t)(c - b->lds) / 8; w <= (size_t)(c - b->lds + bytes - 1) / 8; ++w) {
         word_state& s = b->words[w];
-        const bool race = write ? ((s.w_epoch == b->epoch && s.w_thread != t) ||
-                                   (s.r_epoch == b->epoch && s.r_thread != t))
-                                : (s.w_epoch == b->epoch && s.w_thread != t);
+        const bool wr = s.w_epoch == b->epoch && s.w_thread != t && !ordered(s.w_thread, s.w_wepoch);
+        const bool rd = s.r_epoch == b->epoch && s.r_thread != t && !ordered(s.r_thread, s.r_wepoch);
+        const bool race = write ? (wr || rd) : wr;
         if (race && g_races.fetch_add(1) < 10)
             std::fprintf(stderr, "emu: LDS race at byte %zu, block (%u,%u,%u), thread %d %s, epoch %d\n", w * 8,
                          t_blockIdx.x, t_blockIdx.y, t_blockIdx.z, t, write ? "writes" : "reads", b->epoch);
         if (write) {
             s.w_epoch = b->epoch;
             s.w_thread = t;
-        } else if (s.r_epoch == b->epoch && s.r_thread != t) {
-            s.r_thread = -2;  // several readers
+            s.w_wepoch = we;
+        } else if (s.r_epoch == b->epoch && s.r_thread != t && !ordered(s.r_thread, s.r_wepoch)) {
+            s.r_thread = -2;  // several unordered readers
         } else {
             s.r_epoch = b->epoch;
             s.r_thread = t;
+            s.r_wepoch = we;
         }
     }
 }
 inline void syncthreads() { g_block->bar->arrive_and_wait(); }
+// wave barrier (every lane of the calling wave): orders the wave's LDS accesses
+inline void wave_barrier() {
+    g_block->wave_bar[t_threadIdx.x >> 6]->arrive_and_wait();
+    ++t_wave_epoch;
+}
 inline int lane() { return (int)(t_threadIdx.x & 63u); }
 inline int wave() { return (int)(t_threadIdx.x >> 6); }
 
@@ -249,4 +261,6 @@ template <typename T> inline T __shfl_xor(T v, int m) {
 #define __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, aux) ::emu::buf_store<::emu::u32x2>(v, r, vo, so)
 #define __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, aux) ::emu::buf_store<::emu::u32x4>(v, r, vo, so)
 #define __builtin_amdgcn_readfirstlane(x) (x)
+#define __builtin_amdgcn_wave_barrier() ::emu::wave_barrier()
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) ::emu::update_dpp(old, src, ctrl, rm, bm, bc)

@@ -41,6 +41,7 @@ CASES = [
     ("tkernel", 6, 0, 10, 2, 0),
     ("tkernel", 6, 1, 8, 3, 1),
     ("tkernel", 2, 1, 14, 1, 1),
+    ("tkernel", 2, 1, 13, 1, 0),  # both fold walks with four values a lane in the second
     ("tkernel", 3, 0, 8, 5, 0),  # transposed recurrences, four signals per workgroup
     ("tkernel", 3, 1, 14, 1, 0),  # ... across several waves
     ("tkernel", 7, 0, 12, 1, 1),
