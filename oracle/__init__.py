@@ -6,10 +6,11 @@ plus the direct O(N^2) DFT / DCT-0 / DST-0 definitions).  Only ``tests/``, the
 smoke check and the CPU-baseline leg of ``bench.py`` may import this package;
 the GPU library never does.
 
-Two builds of the same C source exist: ``f64`` (REAL = double, the truth) and
+Three builds of the same C source exist: ``f64`` (REAL = double, the truth),
 ``f32`` (REAL = float, the same-precision emulation used to state per-variant
-bounds).  Both are compiled with ``-O2 -ffp-contract=off`` and no fast-math so
-that every rounding happens where the source says it does.
+bounds) and ``q29`` (32-bit fixed point with Q2.29 constants, variants 1, 3,
+5, 7; Sec. 7.2 / 7.4).  All are compiled with ``-O2 -ffp-contract=off`` and no
+fast-math so that every rounding happens where the source says it does.
 """
 from __future__ import annotations
 
@@ -22,7 +23,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "amqft_oracle.c")
-_LIBS = {"f64": ("double", "liboracle_f64.so"), "f32": ("float", "liboracle_f32.so")}
+_LIBS = {"f64": ("double", "liboracle_f64.so"), "f32": ("float", "liboracle_f32.so"),
+         "q29": (None, "liboracle_q29.so")}
 _lock = threading.Lock()
 _loaded: dict = {}
 
@@ -46,8 +48,9 @@ def build(force: bool = False) -> None:
         if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(_SRC):
             continue
         tmp = out + ".tmp%d" % os.getpid()
+        mode = "-DORACLE_FIXED" if ctype is None else "-DORACLE_REAL=%s" % ctype
         cmd = ["gcc", "-std=gnu99", "-O2", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", "-DORACLE_REAL=%s" % ctype, _SRC, "-o", tmp, "-lm"]
+               "-fPIC", "-shared", mode, _SRC, "-o", tmp, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, out)
 
@@ -66,17 +69,24 @@ def _lib(prec: str = "f64"):
         lib.oracle_cdft.argtypes = [L, L, ctypes.c_int, P, P, P, P, P, P]
         lib.oracle_rdft.argtypes = [L, ctypes.c_int, P, P, P, P, P]
         lib.oracle_sub.argtypes = [ctypes.c_int, L, L, ctypes.c_int, P, P, P, P]
-        lib.oracle_dft_direct.argtypes = [L, L, ctypes.c_int, P, P, P, P]
-        lib.oracle_dcst_direct.argtypes = [ctypes.c_int, L, P, P, P, P]
         want = 8 if prec == "f64" else 4
-        if lib.oracle_real_size() != want:
-            raise RuntimeError("oracle build %s has the wrong REAL size" % name)
+        if lib.oracle_real_size() != want or lib.oracle_is_fixed() != (prec == "q29"):
+            raise RuntimeError("oracle build %s is not the %s build" % (name, prec))
+        if prec == "q29":
+            I = ctypes.c_int
+            lib.oracle_fixed_wraps.restype = ctypes.c_longlong
+            lib.oracle_fixed_mul.argtypes = [I, I]
+            lib.oracle_fixed_half.argtypes = [I]
+            lib.oracle_fixed_konst.argtypes = [I, L, L]
+        else:
+            lib.oracle_dft_direct.argtypes = [L, L, ctypes.c_int, P, P, P, P]
+            lib.oracle_dcst_direct.argtypes = [ctypes.c_int, L, P, P, P, P]
         _loaded[prec] = lib
         return lib
 
 
 def _dt(prec):
-    return np.float64 if prec == "f64" else np.float32
+    return {"f64": np.float64, "f32": np.float32, "q29": np.int32}[prec]
 
 
 def _ptr(a):
@@ -112,6 +122,44 @@ def cdft(x, variant: int = 4, prec: str = "f64", counts: bool = False, touched: 
     if touched:
         out.append(tch[: n // 4].copy())
     return out[0] if len(out) == 1 else tuple(out)
+
+
+def cdft_fixed(xr, xi, variant: int = 1, counts: bool = False):
+    """Fixed-point AM-QFT CDFT (the ``q29`` build) of the last axis of the
+    int32 arrays ``xr``, ``xi`` (real and imaginary parts, in units of the
+    input's last bit).  Variants 1, 3, 5, 7 only.  Returns int32 arrays (Xr, Xi)
+    and the number of results that wrapped around the int32 range."""
+    xr = np.asarray(xr)
+    xi = np.asarray(xi)
+    assert xr.shape == xi.shape
+    n = xr.shape[-1]
+    batch = int(np.prod(xr.shape[:-1], dtype=np.int64)) if xr.ndim > 1 else 1
+    for a in (xr, xi):
+        if np.any(a != a.astype(np.int32)):
+            raise ValueError("fixed-point input must be int32 values")
+    ar = np.ascontiguousarray(xr, dtype=np.int32).reshape(batch, n)
+    ai = np.ascontiguousarray(xi, dtype=np.int32).reshape(batch, n)
+    Xr = np.empty_like(ar)
+    Xi = np.empty_like(ai)
+    lib = _lib("q29")
+    cnt = Counts()
+    with _lock:
+        lib.oracle_fixed_wraps()
+        rc = lib.oracle_cdft(n, batch, int(variant), _ptr(ar), _ptr(ai), _ptr(Xr), _ptr(Xi),
+                             ctypes.byref(cnt), None)
+        wraps = int(lib.oracle_fixed_wraps())
+    if rc != 0:
+        raise ValueError("fixed-point oracle rejected n=%d variant=%d" % (n, variant))
+    out = (Xr.reshape(xr.shape), Xi.reshape(xr.shape), wraps)
+    return out + (cnt.as_dict(),) if counts else out
+
+
+def fixed_scalar(op: str, *args) -> int:
+    """The fixed-point build's scalar rules: ``mul`` (a, k), ``half`` (a),
+    ``konst`` (family 0 = 2cos / 1 = 2sin, j, L), ``base_const`` ()."""
+    lib = _lib("q29")
+    return int({"mul": lib.oracle_fixed_mul, "half": lib.oracle_fixed_half,
+                "konst": lib.oracle_fixed_konst, "base_const": lib.oracle_fixed_base_const}[op](*args))
 
 
 def cdft_adjoint(g, variant: int = 4, prec: str = "f64"):

@@ -16,6 +16,19 @@
  *   - REAL is double for the truth build and float for the same-precision
  *     emulation build; trigonometric constants are always evaluated in double
  *     and rounded once to REAL.
+ *   - The fixed-point build (ORACLE_FIXED; Sec. 7.2 binary translations,
+ *     Sec. 7.4 fixed-point implementations) holds every value as a 32-bit
+ *     two's-complement integer in units of the input's last bit, and each
+ *     constant as round(f * 2^29) (Q2.29; f in (-2, 2): the 2cos / 2sin
+ *     families of variants 1, 3, 5, 7 -- the 1/(2cos) / 1/(2sin) families of
+ *     the other four are unbounded and have no such format).  Additions are
+ *     exact; a product a * k is round((a k) / 2^29) and a halving is
+ *     round(a / 2), both to nearest with ties away from zero (the binary
+ *     translation of the magnitude, sign restored: rounding commutes with
+ *     negation, so a sign flip anywhere in the data changes no rounding); a
+ *     result outside int32 wraps and is counted.  Additions being exact, the
+ *     result depends only on which values are rounded, not on the order of
+ *     the sums.
  *   - Every real addition/subtraction, multiplication by a constant and
  *     halving (binary translation, Sec. 7.2) goes through add/sub/mul/half so
  *     that the counts can be compared with Tables "tab:costo_varianti" and
@@ -32,10 +45,21 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef ORACLE_FIXED
+typedef int32_t REAL;
+#define Q_FRAC 29
+static long long g_wraps; /* results that left the int32 range */
+static REAL wrap32(long long v)
+{
+    if (v < INT32_MIN || v > INT32_MAX) g_wraps++;
+    return (REAL)(int32_t)(uint32_t)(uint64_t)v;
+}
+#else
 #ifndef ORACLE_REAL
 #define ORACLE_REAL double
 #endif
 typedef ORACLE_REAL REAL;
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -58,10 +82,27 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 /* counted arithmetic                                                   */
 /* ------------------------------------------------------------------ */
+#ifdef ORACLE_FIXED
+static REAL add(ctx_t *c, REAL a, REAL b) { if (c->cnt) c->cnt->adds++; return wrap32((long long)a + b); }
+static REAL sub(ctx_t *c, REAL a, REAL b) { if (c->cnt) c->cnt->adds++; return wrap32((long long)a - b); }
+/* round(v / 2^s) to nearest, ties away from zero */
+static long long round_shift(long long v, int s)
+{
+    const long long h = 1LL << (s - 1);
+    return v >= 0 ? (v + h) >> s : -((-v + h) >> s);
+}
+static REAL mul(ctx_t *c, REAL a, REAL k)
+{
+    if (c->cnt) c->cnt->mults++;
+    return wrap32(round_shift((long long)a * k, Q_FRAC));
+}
+static REAL half(ctx_t *c, REAL a) { if (c->cnt) c->cnt->halves++; return wrap32(round_shift(a, 1)); }
+#else
 static REAL add(ctx_t *c, REAL a, REAL b) { if (c->cnt) c->cnt->adds++; return a + b; }
 static REAL sub(ctx_t *c, REAL a, REAL b) { if (c->cnt) c->cnt->adds++; return a - b; }
 static REAL mul(ctx_t *c, REAL a, REAL k) { if (c->cnt) c->cnt->mults++; return a * k; }
 static REAL half(ctx_t *c, REAL a) { if (c->cnt) c->cnt->halves++; return a * (REAL)0.5; }
+#endif
 
 /* families of stored constants, Sec. 7.1 */
 enum { COS2 = 0, SIN2 = 1, SEC2 = 2, CSC2 = 3 };
@@ -73,6 +114,13 @@ static REAL konst(ctx_t *c, int fam, long j, long L)
 {
     long p = j * (c->N / L);
     if (c->touched && p >= 0 && p < c->N / 4) c->touched[p] = 1;
+#ifdef ORACLE_FIXED
+    /* the exact f(2 pi j / L), in long double, rounded once to Q2.29 */
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long double al = 2.0L * pi * (long double)j / (long double)L;
+    long double f = fam == COS2 ? 2.0L * cosl(al) : 2.0L * sinl(al);
+    return (REAL)llroundl(f * (long double)(1L << Q_FRAC));
+#endif
     double a = 2.0 * M_PI * (double)j / (double)L;
     double v;
     switch (fam) {
@@ -88,7 +136,11 @@ static REAL konst(ctx_t *c, int fam, long j, long L)
 static REAL base_const(ctx_t *c)
 {
     if (c->cnt) c->cnt->base_const_uses++;
+#ifdef ORACLE_FIXED
+    return (REAL)llroundl(cosl(3.141592653589793238462643383279502884L / 4.0L) * (long double)(1L << Q_FRAC));
+#else
     return (REAL)cos(M_PI / 4.0);
+#endif
 }
 
 static REAL *alloc(long n)
@@ -499,6 +551,9 @@ int oracle_cdft(long n, long batch, int variant, const REAL *xr, const REAL *xi,
                 REAL *Xr, REAL *Xi, oracle_counts *cnt, unsigned char *touched)
 {
     if (!is_pow2(n) || variant < 1 || variant > 8 || batch < 0) return -1;
+#ifdef ORACLE_FIXED
+    if (variant % 2 == 0) return -2; /* unbounded constants: no Q2.29 form */
+#endif
     ctx_t c = {variant, n, cnt, touched};
     for (long b = 0; b < batch; b++)
         cdft(&c, n, xr + b * n, xi + b * n, Xr + b * n, Xi + b * n);
@@ -510,6 +565,9 @@ int oracle_rdft(long n, int variant, const REAL *r, REAL *Rr, REAL *Ri,
                 oracle_counts *cnt, unsigned char *touched)
 {
     if (!is_pow2(n) || variant < 1 || variant > 8) return -1;
+#ifdef ORACLE_FIXED
+    if (variant % 2 == 0) return -2;
+#endif
     ctx_t c = {variant, n, cnt, touched};
     rdft(&c, n, r, Rr, Ri);
     return 0;
@@ -521,6 +579,9 @@ int oracle_sub(int kind, long L, long ntop, int variant, const REAL *s, REAL *S,
                oracle_counts *cnt, unsigned char *touched)
 {
     if (!is_pow2(L) || variant < 1 || variant > 8 || ntop < L) return -1;
+#ifdef ORACLE_FIXED
+    if (variant % 2 == 0) return -2;
+#endif
     ctx_t c = {variant, ntop, cnt, touched};
     switch (kind) {
     case K_DCT: if (L < 2) return -1; dct(&c, L, s, S); break;
@@ -536,6 +597,7 @@ int oracle_sub(int kind, long L, long ntop, int variant, const REAL *s, REAL *S,
     return 0;
 }
 
+#ifndef ORACLE_FIXED
 /* ------------------------------------------------------------------ */
 /* Direct definitions (O(N^2)), evaluated in long double with the       */
 /* product n*k reduced modulo the periodization before the trig call.   */
@@ -585,5 +647,20 @@ int oracle_dcst_direct(int is_sine, long L, const REAL *s, const unsigned char *
     return 0;
 }
 
+#endif /* !ORACLE_FIXED */
+
 /* size of REAL, so the loader can check which build it has */
 int oracle_real_size(void) { return (int)sizeof(REAL); }
+
+#ifdef ORACLE_FIXED
+int oracle_is_fixed(void) { return 1; }
+/* wrapped results since the last call (and reset) */
+long long oracle_fixed_wraps(void) { long long w = g_wraps; g_wraps = 0; return w; }
+/* the scalar rules, for the pins */
+int oracle_fixed_mul(int a, int k) { ctx_t c = {1, 4, NULL, NULL}; return mul(&c, a, k); }
+int oracle_fixed_half(int a) { ctx_t c = {1, 4, NULL, NULL}; return half(&c, a); }
+int oracle_fixed_konst(int fam, long j, long L) { ctx_t c = {1, L, NULL, NULL}; return konst(&c, fam, j, L); }
+int oracle_fixed_base_const(void) { ctx_t c = {1, 8, NULL, NULL}; return base_const(&c); }
+#else
+int oracle_is_fixed(void) { return 0; }
+#endif
