@@ -44,13 +44,28 @@ typedef enum {
     AMQFT_V5 = 5, AMQFT_V6 = 6, AMQFT_V7 = 7, AMQFT_V8 = 8
 } amqft_variant;
 
-/* Storage type of the complex data; arithmetic is FP64 for AMQFT_C128 and
- * FP32 for the other three. */
+/* Storage type of the complex data; arithmetic is FP64 for AMQFT_C128,
+ * FP32 for AMQFT_C64 / C32H / C32B and 32-bit fixed point for AMQFT_C32I. */
 typedef enum {
     AMQFT_C128 = 0, /* complex double: 16 bytes per point            */
     AMQFT_C64 = 1,  /* complex float: 8 bytes per point              */
     AMQFT_C32H = 2, /* FP16 (re, im) pairs, FP32 arithmetic: 4 bytes */
-    AMQFT_C32B = 3  /* BF16 (re, im) pairs, FP32 arithmetic: 4 bytes */
+    AMQFT_C32B = 3, /* BF16 (re, im) pairs, FP32 arithmetic: 4 bytes */
+    /* Fixed point (Sec. 7.2: halvings are binary translations; Sec. 7.4:
+     * fixed-point implementations): (re, im) int32 pairs, 8 bytes per point,
+     * in units of the input's last bit; the output is the unnormalized DFT in
+     * the same units.  Constants are round(f 2^29) (Q2.29), so only the
+     * variants whose constants are 2cos / 2sin (1, 3, 5, 7) have this form;
+     * 2^8 <= n <= 2^14.  Sums are exact and wrap modulo 2^32; a product with
+     * a constant k is round(a k / 2^29), a halving round(a / 2), both to
+     * nearest with ties away from zero.  The caller picks the input scale
+     * (measured with the oracle on random, sign, tone and constant inputs):
+     * variant 1 keeps every value inside int32 for |x| <= 2^15 up to
+     * n = 2^14; variant 3 scales values near harmonic n/4 up by about
+     * n/(4 pi) and needs |x| <= 2^12 at n = 2^12, 2^10 at 2^13 and 2^8 at
+     * 2^14; variants 5 and 7 grow as their floating-point versions do and
+     * wrap at |x| <= 2^15 from n = 2^12 (variant 5) and 2^10 (variant 7). */
+    AMQFT_C32I = 4
 } amqft_dtype;
 
 typedef enum {

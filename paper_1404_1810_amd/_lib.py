@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libamqft.so")
 
 # enums of include/amqft.h
-C128, C64, C32H, C32B = 0, 1, 2, 3
+C128, C64, C32H, C32B, C32I = 0, 1, 2, 3, 4
 OK, ERR_INVALID_ARG, ERR_NOT_POW2, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP = range(6)
 RDFT, DCT0, DST0 = 0, 1, 2
 FLAG_ONTHEFLY_CONSTANTS = 1

@@ -7,6 +7,8 @@ Storage conventions (last dimension = the transform axis):
   complex128 / complex64 tensors       -> AMQFT_C128 / AMQFT_C64
   float16 / bfloat16 tensors (..., n, 2) -> AMQFT_C32H / AMQFT_C32B
                                            (interleaved re/im, FP32 math)
+  int32 tensors (..., n, 2)              -> AMQFT_C32I (fixed point, variants
+                                           1, 3, 5, 7, Q2.29 constants)
 """
 from __future__ import annotations
 
@@ -17,7 +19,8 @@ import torch
 from . import _lib
 
 _DTYPES = {torch.complex128: _lib.C128, torch.complex64: _lib.C64,
-           torch.float16: _lib.C32H, torch.bfloat16: _lib.C32B}
+           torch.float16: _lib.C32H, torch.bfloat16: _lib.C32B, torch.int32: _lib.C32I}
+_PAIRS = (_lib.C32H, _lib.C32B, _lib.C32I)  # storage with a trailing (re, im) dimension
 
 
 def _storage(x: torch.Tensor):
@@ -25,9 +28,9 @@ def _storage(x: torch.Tensor):
     if x.dtype not in _DTYPES:
         raise TypeError("unsupported dtype %s" % x.dtype)
     dt = _DTYPES[x.dtype]
-    if dt in (_lib.C32H, _lib.C32B):
+    if dt in _PAIRS:
         if x.dim() < 2 or x.shape[-1] != 2:
-            raise ValueError("half/bfloat16 storage must have a trailing (re, im) dimension of size 2")
+            raise ValueError("half/bfloat16/int32 storage must have a trailing (re, im) dimension of size 2")
         n = x.shape[-2]
         batch = x.numel() // (2 * n) if n else 0
     else:
@@ -244,7 +247,7 @@ class ManyPlan:
         dt = _DTYPES.get(t.dtype)
         if dt != self.dtype:
             raise ValueError("%s has dtype %s, the plan %d" % (name, t.dtype, self.dtype))
-        npts = t.numel() // (2 if dt in (_lib.C32H, _lib.C32B) else 1)
+        npts = t.numel() // (2 if dt in _PAIRS else 1)
         if npts < self.total:
             raise ValueError("%s holds %d points, the plan's offsets reach %d" % (name, npts, self.total))
 

@@ -89,7 +89,7 @@ amqft_status hip_fail(hipError_t e) {
 }
 
 bool valid_variant(int v) { return v >= 1 && v <= 8; }
-bool valid_dtype(int t) { return t >= 0 && t <= 3; }
+bool valid_dtype(int t) { return t >= 0 && t <= 4; }
 constexpr unsigned kAllFlags = AMQFT_FLAG_ONTHEFLY_CONSTANTS | AMQFT_FLAG_NO_AUTOTUNE | AMQFT_FLAG_FORCE_MULTIPASS |
                                AMQFT_FLAG_FORCE_LARGE | AMQFT_FLAG_TRANSPOSED_ADJOINT;
 
@@ -116,8 +116,7 @@ int log2_exact(int64_t n) {
 int max_lds_log2(int dtype) { return dtype == AMQFT_C128 ? kMaxLdsLog2F64 : kMaxLdsLog2F32; }
 
 // f(2 pi p / n) for the variant's family (Sec. 7.1), evaluated in long double
-// and rounded to double; the caller rounds once more to the working type.
-double family_value(int fam, int64_t p, int64_t n) {
+long double family_value_ld(int fam, int64_t p, int64_t n) {
     const long double pi = 3.141592653589793238462643383279502884L;
     const long double a = 2.0L * pi * (long double)p / (long double)n;
     long double v;
@@ -127,7 +126,15 @@ double family_value(int fam, int64_t p, int64_t n) {
     case 2: v = 2.0L * sinl(a); break;
     default: v = 1.0L / (2.0L * sinl(a)); break;
     }
-    return (double)v;
+    return v;
+}
+
+// the same rounded to double; the caller rounds once more to the working type
+double family_value(int fam, int64_t p, int64_t n) { return (double)family_value_ld(fam, p, n); }
+
+// fixed point: the constant's Q2.29 integer round(f 2^29), ties away from zero
+int32_t q29_value(int fam, int64_t p, int64_t n) {
+    return (int32_t)llroundl(family_value_ld(fam, p, n) * (long double)(1 << 29));
 }
 
 amqft_status build_constants(amqft_plan_s* p, int log2n) {
@@ -137,6 +144,19 @@ amqft_status build_constants(amqft_plan_s* p, int log2n) {
     p->ktab_log2n = log2n < 2 ? 2 : log2n;
     p->ktab_host.assign((size_t)q, 0.0);
     const bool f64 = p->dtype == AMQFT_C128;
+    if (p->dtype == AMQFT_C32I) {
+        // the kernels read the Q2.29 integers; the host copy holds their values
+        std::vector<int32_t> ti((size_t)q, 0);
+        for (int64_t i = 1; i < q; ++i) {
+            ti[i] = q29_value(fam, i, n);
+            p->ktab_host[i] = ldexp((double)ti[i], -29);
+        }
+        const size_t bytes = (size_t)q * sizeof(int32_t);
+        hipError_t e = hipMalloc(&p->ktab, bytes < 16 ? 16 : bytes);
+        if (e != hipSuccess) { p->ktab = nullptr; return hip_fail(e); }
+        e = hipMemcpy(p->ktab, ti.data(), bytes, hipMemcpyHostToDevice);
+        return e == hipSuccess ? AMQFT_OK : hip_fail(e);
+    }
     std::vector<float> tf;
     if (!f64) tf.assign((size_t)q, 0.f);
     for (int64_t i = 1; i < q; ++i) {
@@ -158,6 +178,12 @@ amqft_status build_constants(amqft_plan_s* p, int log2n) {
 }
 
 amqft_status prime(int variant, int dtype) {
+    if (dtype == AMQFT_C32I) {
+        // fixed point runs on the compile-time kernels only
+        hipError_t e = prime_kA(variant, dtype);
+        if (e == hipSuccess) e = prime_kB(variant, dtype);
+        return e == hipSuccess ? AMQFT_OK : hip_fail(e);
+    }
     hipError_t e = prime_lds(variant, dtype);
     if (e == hipSuccess) e = prime_multipass(variant, dtype);
     if (e == hipSuccess) e = prime_kL(variant, dtype);
@@ -539,6 +565,10 @@ amqft_status amqft_plan_create(amqft_plan* out, int64_t n, int64_t batch, amqft_
     if (logn < 0) return AMQFT_ERR_NOT_POW2;
     if (logn > AMQFT_MAX_LOG2N) return AMQFT_ERR_UNSUPPORTED;
     if ((flags & kForceFlags) == kForceFlags) return AMQFT_ERR_UNSUPPORTED;
+    if (dtype == AMQFT_C32I &&
+        ((flags & kForceFlags) || !(kA_supported((int)variant, logn, AMQFT_C32I) ||
+                                    kB_supported((int)variant, logn, AMQFT_C32I))))
+        return AMQFT_ERR_UNSUPPORTED;
     if ((flags & AMQFT_FLAG_TRANSPOSED_ADJOINT) &&
         ((flags & kForceFlags) || !transposed_adjoint_supported((int)variant, logn, (int)dtype)))
         return AMQFT_ERR_UNSUPPORTED;
@@ -560,7 +590,7 @@ amqft_status amqft_plan_create_real(amqft_plan* out, int64_t n, int64_t batch, a
     const int logn = log2_exact(n);
     if (logn < 0) return AMQFT_ERR_NOT_POW2;
     if (flags & (kForceFlags | AMQFT_FLAG_TRANSPOSED_ADJOINT)) return AMQFT_ERR_UNSUPPORTED;
-    if (dtype != AMQFT_C128 && dtype != AMQFT_C64) return AMQFT_ERR_UNSUPPORTED;
+    if (dtype != AMQFT_C128 && dtype != AMQFT_C64) return AMQFT_ERR_UNSUPPORTED;  // also no fixed point
     if (logn < 2 || logn > max_lds_log2((int)dtype)) return AMQFT_ERR_UNSUPPORTED;
     if (batch > (int64_t(1) << 40)) return AMQFT_ERR_UNSUPPORTED;
     amqft_plan_s* p = new (std::nothrow) amqft_plan_s();
@@ -590,6 +620,7 @@ amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_
     if (count > 0 && (!lengths_host || !offsets_host)) return AMQFT_ERR_INVALID_ARG;
     if (flags & ~kAllFlags) return AMQFT_ERR_INVALID_ARG;
     if (flags & AMQFT_FLAG_TRANSPOSED_ADJOINT) return AMQFT_ERR_UNSUPPORTED;
+    if (dtype == AMQFT_C32I) return AMQFT_ERR_UNSUPPORTED;
     int maxlog = 2;
     for (int64_t i = 0; i < count; ++i) {
         const int l = log2_exact(lengths_host[i]);
@@ -713,6 +744,7 @@ amqft_status amqft_power_loss_grad(amqft_plan p, const void* x, const void* w, v
     if (p->batch == 0) return AMQFT_OK;
     if (!x || !w || !grad || !loss) return AMQFT_ERR_INVALID_ARG;
     if (p->logn < 2 || p->multipass || p->large || p->real_kind >= 0) return AMQFT_ERR_UNSUPPORTED;
+    if (p->dtype == AMQFT_C32I) return AMQFT_ERR_UNSUPPORTED;
     loss_launch a{};
     a.variant = p->variant;
     a.dtype = p->dtype;
@@ -846,6 +878,13 @@ amqft_status amqft_plan_constants(amqft_plan p, int64_t n, double* table_host, i
     }
     // generated on the device: copy the table back as the kernels read it
     const size_t q = size_t(1) << (p->ktab_log2n - 2);
+    if (p->dtype == AMQFT_C32I) {
+        std::vector<int32_t> ti(q);
+        hipError_t e = hipMemcpy(ti.data(), p->ktab, q * sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e);
+        for (int64_t i = 0; i < n / 4; ++i) table_host[i] = ldexp((double)ti[(size_t)(i << shift)], -29);
+        return AMQFT_OK;
+    }
     const bool f64 = p->dtype == AMQFT_C128;
     std::vector<double> td;
     std::vector<float> tf;

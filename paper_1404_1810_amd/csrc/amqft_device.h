@@ -12,6 +12,41 @@
 
 namespace amqft {
 
+// ---------------------------------------------------------------------------
+// 32-bit fixed point (Sec. 7.2: the halvings are binary translations; Sec.
+// 7.4: fixed-point implementations).  A value is an int32 in units of the
+// input's last bit; a constant f (|f| < 4) is round(f 2^29), ties away from
+// zero (Q2.29: the 2cos / 2sin families, cos(pi/4), the +-1 weights and the
+// halving 1/2).  Sums wrap modulo 2^32 and are exact otherwise; a product
+// a * k is round(a k / 2^29) to nearest, ties away from zero (the binary
+// translation of the 64-bit product's magnitude, sign restored), so that
+// a * (1/2) is the rounded halving and rounding commutes with negation: the
+// kernels may carry a value negated or multiplied by -i (the transposed
+// combine does) without changing any rounding.  Every product of the
+// transform has a constant as one factor, so the operator needs no notion of
+// which operand is data.  With exact sums the result depends only on which
+// values are rounded, not on the order in which the sums are formed.
+// ---------------------------------------------------------------------------
+struct fx32 {
+    int v;
+    fx32() = default;
+    __host__ __device__ constexpr explicit fx32(double f)
+        : v((int)(f * 536870912.0 + (f < 0 ? -0.5 : 0.5))) {}
+    static __host__ __device__ constexpr fx32 raw(int x) {
+        fx32 r(0.0);
+        r.v = x;
+        return r;
+    }
+};
+__device__ __forceinline__ fx32 operator+(fx32 a, fx32 b) { return fx32::raw((int)((unsigned)a.v + (unsigned)b.v)); }
+__device__ __forceinline__ fx32 operator-(fx32 a, fx32 b) { return fx32::raw((int)((unsigned)a.v - (unsigned)b.v)); }
+__device__ __forceinline__ fx32 operator-(fx32 a) { return fx32::raw((int)(0u - (unsigned)a.v)); }
+__device__ __forceinline__ fx32 operator*(fx32 a, fx32 k) {
+    const long long p = (long long)a.v * k.v;
+    const long long m = ((p < 0 ? -p : p) + (1ll << 28)) >> 29;
+    return fx32::raw((int)(unsigned)(p < 0 ? -m : m));
+}
+
 // aligned to its full size, so that LDS and global accesses of one complex
 // value are single 64-bit (FP32) or 128-bit (FP64) transactions
 template <typename R>
@@ -24,6 +59,7 @@ struct alignas(2 * sizeof(R)) cx {
 template <typename R> struct vec2;
 template <> struct vec2<float> { typedef float T __attribute__((ext_vector_type(2))); };
 template <> struct vec2<double> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct vec2<fx32> { typedef int T __attribute__((ext_vector_type(2))); };
 template <typename R>
 __device__ __forceinline__ cx<R> ldc(const cx<R>* p) {
     const typename vec2<R>::T v = *reinterpret_cast<const typename vec2<R>::T*>(p);
@@ -35,6 +71,17 @@ __device__ __forceinline__ void stc(cx<R>* p, cx<R> a) {
     v.x = a.re;
     v.y = a.im;
     *reinterpret_cast<typename vec2<R>::T*>(p) = v;
+}
+
+__device__ __forceinline__ cx<fx32> ldc(const cx<fx32>* p) {
+    const vec2<fx32>::T v = *reinterpret_cast<const vec2<fx32>::T*>(p);
+    return {fx32::raw(v.x), fx32::raw(v.y)};
+}
+__device__ __forceinline__ void stc(cx<fx32>* p, cx<fx32> a) {
+    vec2<fx32>::T v;
+    v.x = a.re.v;
+    v.y = a.im.v;
+    *reinterpret_cast<vec2<fx32>::T*>(p) = v;
 }
 
 template <typename R>
@@ -51,6 +98,7 @@ __device__ __forceinline__ cx<R> cconj(cx<R> a) { return {a.re, -a.im}; }
 template <typename R> __device__ __forceinline__ R cos_pi_4();
 template <> __device__ __forceinline__ float cos_pi_4<float>() { return 0.70710678118654752440f; }
 template <> __device__ __forceinline__ double cos_pi_4<double>() { return 0.70710678118654752440; }
+template <> __device__ __forceinline__ fx32 cos_pi_4<fx32>() { return fx32::raw(379625062); }  // round(2^29 / sqrt 2)
 
 // ---------------------------------------------------------------------------
 // storage types: interleaved (re, im) pairs
@@ -102,6 +150,13 @@ template <> struct storage<bf16x2> {
         o.im = f32_to_bf16(v.im);
         *p = o;
     }
+};
+
+// complex 32-bit fixed point: (re, im) int32 pairs
+template <> struct storage<int2> {
+    using R = fx32;
+    static __device__ __forceinline__ cx<fx32> ld(const int2* p) { int2 v = *p; return {fx32::raw(v.x), fx32::raw(v.y)}; }
+    static __device__ __forceinline__ void st(int2* p, cx<fx32> v) { *p = make_int2(v.re.v, v.im.v); }
 };
 
 // ---------------------------------------------------------------------------

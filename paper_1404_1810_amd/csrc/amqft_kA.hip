@@ -773,6 +773,8 @@ hipError_t prime_kL_n() {
 bool kA_supported(int variant, int logn, int dtype) {
     if (variant != 1 && variant != 4 && variant != 5 && variant != 8) return false;
     if (dtype == 0) return logn >= 8 && logn <= 13;
+    // fixed point: the variants whose constants (2cos, 2sin) have a Q2.29 form
+    if (dtype == 4) return (variant == 1 || variant == 5) && logn >= 8 && logn <= 14;
     return logn >= 8 && logn <= 14;  // FP32 arithmetic: FP32, FP16 and BF16 storage
 }
 
@@ -825,6 +827,9 @@ static hipError_t prime_kA_v(int dtype) {
         return e;
     }
     case 2: return prime_kA_n<V, __half2, 8>();
+    case 4:
+        if constexpr (V == 1 || V == 5) return prime_kA_n<V, int2, 8>();
+        else return hipErrorInvalidValue;
     default: return prime_kA_n<V, bf16x2, 8>();
     }
 }
@@ -893,6 +898,9 @@ static hipError_t launch_kA_t(const lds_launch& a, hipStream_t st) {
     case 0: return launch_kA_s<V, double2>(a, st);
     case 1: return launch_kA_s<V, float2>(a, st);
     case 2: return launch_kA_s<V, __half2>(a, st);
+    case 4:
+        if constexpr (V == 1 || V == 5) return launch_kA_s<V, int2>(a, st);
+        else return hipErrorInvalidValue;
     default: return launch_kA_s<V, bf16x2>(a, st);
     }
 }

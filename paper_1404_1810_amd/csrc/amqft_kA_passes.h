@@ -666,12 +666,22 @@ template <typename R>
 __device__ __forceinline__ cx<R> shfl_dn_c(cx<R> v, int d) {
     return cx<R>{__shfl_down(v.re, d), __shfl_down(v.im, d)};
 }
+__device__ __forceinline__ cx<fx32> shfl_up_c(cx<fx32> v, int d) {
+    return cx<fx32>{fx32::raw(__shfl_up(v.re.v, d)), fx32::raw(__shfl_up(v.im.v, d))};
+}
+__device__ __forceinline__ cx<fx32> shfl_dn_c(cx<fx32> v, int d) {
+    return cx<fx32>{fx32::raw(__shfl_down(v.re.v, d)), fx32::raw(__shfl_down(v.im.v, d))};
+}
 
 // lane i receives lane i - D (UP) or lane i + D inside its row of 16 lanes
 // (data-parallel-primitive moves: a VALU operation, no LDS traffic)
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ fx32 dpp_mov(fx32 v) {
+    return fx32::raw(__builtin_amdgcn_update_dpp(0, v.v, CTRL, 0xF, 0xF, false));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {

@@ -1122,6 +1122,9 @@ hipError_t launch_kB_v(const lds_launch& a, hipStream_t st) {
     case 0: return launch_kB_s<VB, double2>(a, st);
     case 1: return launch_kB_s<VB, float2>(a, st);
     case 2: return launch_kB_s<VB, __half2>(a, st);
+    case 4:
+        if constexpr (VB == 3 || VB == 7) return launch_kB_s<VB, int2>(a, st);
+        else return hipErrorInvalidValue;
     default: return launch_kB_s<VB, bf16x2>(a, st);
     }
 }
@@ -1132,6 +1135,9 @@ hipError_t prime_kB_v(int dtype) {
     case 0: return prime_kB_n<VB, double2, 8>();
     case 1: return prime_kB_n<VB, float2, 8>();
     case 2: return prime_kB_n<VB, __half2, 8>();
+    case 4:
+        if constexpr (VB == 3 || VB == 7) return prime_kB_n<VB, int2, 8>();
+        else return hipErrorInvalidValue;
     default: return prime_kB_n<VB, bf16x2, 8>();
     }
 }
@@ -1141,6 +1147,8 @@ hipError_t prime_kB_v(int dtype) {
 bool kB_supported(int variant, int logn, int dtype) {
     if (variant != 2 && variant != 3 && variant != 6 && variant != 7) return false;
     if (dtype == 0) return logn >= 8 && logn <= 13;
+    // fixed point: the variants whose constants (2cos, 2sin) have a Q2.29 form
+    if (dtype == 4) return (variant == 3 || variant == 7) && logn >= 8 && logn <= 14;
     return logn >= 8 && logn <= 14;
 }
 

@@ -581,6 +581,9 @@ hipError_t fill_table_device(void* ktab, int variant, int dtype, int logn, hipSt
     if (dtype == 0)
         hipLaunchKernelGGL((amqft_fill_table_kernel<double>), grid, dim3(256), 0, st, static_cast<double*>(ktab),
                            const_family(variant), logn);
+    else if (dtype == 4)
+        hipLaunchKernelGGL((amqft_fill_table_kernel<fx32>), grid, dim3(256), 0, st, static_cast<fx32*>(ktab),
+                           const_family(variant), logn);
     else
         hipLaunchKernelGGL((amqft_fill_table_kernel<float>), grid, dim3(256), 0, st, static_cast<float*>(ktab),
                            const_family(variant), logn);
@@ -588,8 +591,8 @@ hipError_t fill_table_device(void* ktab, int variant, int dtype, int logn, hipSt
 }
 
 void describe_lds(const lds_launch& a, char* buf, size_t len) {
-    static const char* st[4] = {"double2", "float2", "__half2", "bf16x2"};
-    const char* sname = st[a.dtype & 3];
+    static const char* st[5] = {"double2", "float2", "__half2", "bf16x2", "int2"};
+    const char* sname = st[a.dtype >= 0 && a.dtype <= 4 ? a.dtype : 1];
     int threads = 0, spw = 1;
     size_t lds = 0;
     if (!a.generic && kA_supported(a.variant, a.logn, a.dtype)) {

@@ -35,6 +35,12 @@ def _transform_header(name: str, text: str) -> str:
         assert a in text and b in text, "ldc / stc bodies changed: update the emulation transform"
         text = text.replace(a, "    ::emu::lds_touch(p, sizeof(cx<R>), false);\n" + a)
         text = text.replace(b, "    ::emu::lds_touch(p, sizeof(cx<R>), true);\n" + b)
+        # the fixed-point overloads
+        a = "    const vec2<fx32>::T v = *reinterpret_cast<const vec2<fx32>::T*>(p);"
+        b = "    *reinterpret_cast<vec2<fx32>::T*>(p) = v;"
+        assert a in text and b in text, "fixed-point ldc / stc bodies changed: update the emulation transform"
+        text = text.replace(a, "    ::emu::lds_touch(p, sizeof(cx<fx32>), false);\n" + a)
+        text = text.replace(b, "    ::emu::lds_touch(p, sizeof(cx<fx32>), true);\n" + b)
     return text
 
 

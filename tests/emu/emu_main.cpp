@@ -3,7 +3,8 @@
 // PATH: lds (the dispatch of launch_lds: compile-time kernels where they
 // exist), generic (the level engine), large (the top/rows/back/bchain
 // kernels of variants 4 and 8 over malloc'd workspaces), tkernel (the
-// transposed compile-time kernel).  DTYPE 0 = complex FP64, 1 = complex FP32.
+// transposed compile-time kernel).  DTYPE 0 = complex FP64, 1 = complex FP32,
+// 4 = complex int32 fixed point (Q2.29 constants).
 // IN / OUT: raw interleaved complex arrays of BATCH x 2^LOGN values.
 // The constant table is built on the host in long double and rounded once.
 #include <cmath>
@@ -18,7 +19,7 @@
 
 using namespace amqft;
 
-static double family_value(int fam, long p, long n) {
+static long double family_value(int fam, long p, long n) {
     const long double pi = 3.141592653589793238462643383279502884L;
     const long double a = 2.0L * pi * (long double)p / (long double)n;
     long double v;
@@ -28,7 +29,7 @@ static double family_value(int fam, long p, long n) {
     case 2: v = 2.0L * sinl(a); break;
     default: v = 1.0L / (2.0L * sinl(a)); break;
     }
-    return (double)v;
+    return v;
 }
 
 int main(int argc, char** argv) {
@@ -49,8 +50,10 @@ int main(int argc, char** argv) {
     const long q = n / 4 > 1 ? n / 4 : 1;
     std::vector<unsigned char> kt((size_t)q * rsz, 0);
     for (long p = 1; p < q; ++p) {
-        const double v = family_value(const_family(variant), p, n);
+        const long double lv = family_value(const_family(variant), p, n);
+        const double v = (double)lv;
         if (dtype == 0) std::memcpy(&kt[p * rsz], &v, 8);
+        else if (dtype == 4) { const int32_t k = (int32_t)llroundl(lv * (long double)(1 << 29)); std::memcpy(&kt[p * rsz], &k, 4); }
         else { const float fv = (float)v; std::memcpy(&kt[p * rsz], &fv, 4); }
     }
     hipError_t e = hipSuccess;

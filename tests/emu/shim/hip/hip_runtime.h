@@ -39,6 +39,8 @@ struct alignas(8) float2 { float x, y; };
 struct alignas(16) int4 { int x, y, z, w; };
 inline double2 make_double2(double a, double b) { return {a, b}; }
 inline float2 make_float2(float a, float b) { return {a, b}; }
+struct alignas(8) int2 { int x, y; };
+inline int2 make_int2(int a, int b) { return {a, b}; }
 
 typedef enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2, hipErrorInvalidSymbol = 13 } hipError_t;
 typedef void* hipStream_t;

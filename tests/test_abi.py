@@ -156,3 +156,26 @@ def test_transposed_adjoint_not_for_many_or_real(lib):
     O = np.array([0, 256, 512], dtype=np.int64)
     assert lib.amqft_plan_create_many(ctypes.byref(h), 2, L.ctypes.data, O.ctypes.data, 4, 1, 16) == _lib.ERR_UNSUPPORTED
     assert lib.amqft_plan_create_real(ctypes.byref(h), 256, 1, 0, 4, 1, 16) == _lib.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n,variant,flags", [(1024, 2, 0), (1024, 4, 0), (1024, 6, 0), (1024, 8, 0),  # 1/(2cos) family
+                                             (128, 1, 0), (1 << 15, 1, 0), (1 << 15, 3, 0),  # outside 2^8..2^14
+                                             (1024, 1, 4), (1024, 3, 8)])  # force flags
+def test_fixed_point_validation(lib, n, variant, flags):
+    """Fixed point (AMQFT_C32I) exists for the variants with 2cos / 2sin
+    constants on the compile-time kernels (2^8 .. 2^14); elsewhere plan
+    creation refuses it before any HIP call."""
+    rc, h = _create(lib, n, variant=variant, dtype=_lib.C32I, flags=flags)
+    assert rc == _lib.ERR_UNSUPPORTED
+    assert not h.value
+
+
+def test_fixed_point_not_for_many_or_real(lib):
+    import numpy as np
+    h = ctypes.c_void_p(3)
+    L = np.array([256, 256], dtype=np.int64)
+    O = np.array([0, 256, 512], dtype=np.int64)
+    assert lib.amqft_plan_create_many(ctypes.byref(h), 2, L.ctypes.data, O.ctypes.data, 1, _lib.C32I, 0) \
+        == _lib.ERR_UNSUPPORTED
+    assert lib.amqft_plan_create_real(ctypes.byref(h), 256, 1, 0, 1, _lib.C32I, 0) == _lib.ERR_UNSUPPORTED
+    assert lib.amqft_exec_noalloc(256, 1, 1, _lib.C32I, 0, None, None, None) == _lib.ERR_INVALID_ARG

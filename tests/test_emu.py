@@ -93,3 +93,36 @@ def test_transposed_program_is_the_dual_variant(emu_exe, tmp_path, vb, logn):
     assert np.array_equal(y, emu), rel(y, emu)
     if vb == 6:  # the skeleton-A twin rounds differently
         assert not np.array_equal(y, oracle.cdft(x, 8, prec="f32"))
+
+
+FIXED_CASES = [
+    # (path, variant, log2 N, batch, conjugated in and out): int32 fixed point
+    ("lds", 1, 12, 2, 0),      # amqft_kA_kernel, M1 recurrences as lane scans
+    ("lds", 5, 9, 3, 1),       # two signals per workgroup, adjoint
+    ("lds", 1, 14, 1, 0),
+    ("tkernel", 3, 12, 1, 0),  # amqft_kB_kernel: the transposed recurrences
+    ("tkernel", 7, 8, 5, 1),
+    ("tkernel", 3, 13, 1, 1),
+]
+
+
+@pytest.mark.parametrize("path,variant,logn,batch,conj", FIXED_CASES)
+def test_fixed_point_kernel_source_is_bit_exact(emu_exe, tmp_path, path, variant, logn, batch, conj):
+    """Fixed point: sums are exact, so the kernels (scans, transposed levels,
+    any order of the sums) must round exactly the values the recursion
+    rounds -- the output equals the fixed-point oracle's bit for bit."""
+    import oracle
+    n = 1 << logn
+    rng = np.random.default_rng(100 + logn + variant)
+    x = rng.integers(-2 ** 15, 2 ** 15, size=(batch, n, 2), dtype=np.int32)
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    x.tofile(fin)
+    r = subprocess.run([emu_exe, path, str(variant), "4", str(logn), str(batch), str(conj), fin, fout],
+                       capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1"))
+    assert r.returncode == 0, r.stderr[-4000:]
+    y = np.fromfile(fout, dtype=np.int32).reshape(batch, n, 2)
+    sgn = -1 if conj else 1  # adjoint: conj(F conj(x)); negation is exact
+    Xr, Xi, wraps = oracle.cdft_fixed(x[..., 0], sgn * x[..., 1], variant)
+    assert np.array_equal(y[..., 0], Xr) and np.array_equal(y[..., 1], sgn * Xi), \
+        (int(np.sum(y[..., 0] != Xr)), int(np.sum(y[..., 1] != sgn * Xi)), wraps)
