@@ -459,6 +459,41 @@ def bench_precision(args, stream):
                         "on-the-fly constants" % B, "sampled_signals": sample, "variants": res}
 
 
+def bench_fixed(args, stream):
+    """Fixed-point AM-QFT (int32 values, Q2.29 constants) on the headline shape:
+    variants 1, 3, 5, 7, inputs |x| < 2^12 (inside int32 for all four up to
+    N = 2^12 here, wraps counted by the oracle), two sampled signals per
+    variant against the fixed-point oracle, bit for bit."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1404_1810_amd import api, inputs
+
+    n, B = args.n, args.batch
+    seed = inputs.SEEDS["fixed_n4096"]
+    xh = inputs.int_pairs(seed, B, n, 12)
+    x = torch.from_numpy(xh).cuda()
+    y = torch.empty_like(x)
+    algo = B * n * 16.0
+    res = {}
+    for v in (1, 3, 5, 7):
+        plan = api.get_plan(n, B, v, 4)
+        r = time_launches(lambda: plan.exec(x, out=y), args.steps, args.warmup, stream)
+        rows = [0, B - 1]
+        got = y[rows].cpu().numpy()
+        Xr, Xi, wraps = oracle.cdft_fixed(xh[rows, :, 0], xh[rows, :, 1], v)
+        exact = bool(np.array_equal(got[..., 0], Xr) and np.array_equal(got[..., 1], Xi))
+        res[str(v)] = {"kernel": plan.describe(), "avg_ms": round(r["avg_ms"], 5),
+                       "hbm_gbs": round(algo / r["avg_ms"] / 1e6, 1),
+                       "frac_of_peak": round(algo / r["avg_ms"] / 1e6 / HBM_PEAK_GBS, 4),
+                       "sampled_bit_exact_vs_fixed_oracle": exact, "oracle_wraps": wraps}
+        log("fixed point variant %d: avg %.4f ms, %.1f GB/s, bit-exact %s" % (v, r["avg_ms"], algo / r["avg_ms"] / 1e6,
+                                                                               exact))
+    return {"workload": "batch %d x N=%d int32 (re, im) pairs, entries uniform on [-2^12, 2^12) seed %d, "
+                        "Q2.29 constants, forward" % (B, n, seed), "variants": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -597,6 +632,9 @@ def main():
         torch.cuda.empty_cache()
         log("fused loss/gradient workload")
         extra["grad"] = bench_grad(args, stream)
+        torch.cuda.empty_cache()
+        log("fixed-point workload")
+        extra["fixed_point"] = bench_fixed(args, stream)
         torch.cuda.empty_cache()
         line["workloads"] = extra
     tr = load_traffic(family, args.variant, n, batch)

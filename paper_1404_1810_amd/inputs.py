@@ -16,7 +16,7 @@ import numpy as np
 
 #: seeds of the five configurations
 SEEDS = {"fp64_n256": 0, "fp32_n4096": 0, "uneven_lengths": 2, "uneven_entries": 3,
-         "grad_x": 0, "grad_w": 1, "fp16_n2p20": 0}
+         "grad_x": 0, "grad_w": 1, "fp16_n2p20": 0, "fixed_n4096": 5}
 
 
 def _rows(seed: int, batch: int, n: int, kind: str, start: int = 0, out: np.ndarray | None = None) -> np.ndarray:
@@ -138,3 +138,9 @@ def to_bf16_bits(a: np.ndarray) -> np.ndarray:
 def from_bf16_bits(b: np.ndarray) -> np.ndarray:
     """Widen raw bfloat16 patterns (uint16) to float32."""
     return (np.ascontiguousarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def int_pairs(seed: int, batch: int, n: int, bits: int) -> np.ndarray:
+    """int32 array (batch, n, 2) of (re, im) pairs uniform on [-2^bits, 2^bits)
+    (fixed-point storage)."""
+    return np.random.default_rng(seed).integers(-2 ** bits, 2 ** bits, size=(batch, n, 2), dtype=np.int32)

@@ -33,8 +33,8 @@ def _scale_bits(variant, logn):
 
 
 def _inputs(seed, batch, n, bits):
-    rng = np.random.default_rng(seed)
-    return rng.integers(-2 ** bits, 2 ** bits, size=(batch, n, 2), dtype=np.int32)
+    from paper_1404_1810_amd import inputs
+    return inputs.int_pairs(seed, batch, n, bits)
 
 
 def _oracle(x, variant, adjoint=False):
