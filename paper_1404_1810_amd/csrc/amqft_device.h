@@ -41,10 +41,11 @@ struct fx32 {
 __device__ __forceinline__ fx32 operator+(fx32 a, fx32 b) { return fx32::raw((int)((unsigned)a.v + (unsigned)b.v)); }
 __device__ __forceinline__ fx32 operator-(fx32 a, fx32 b) { return fx32::raw((int)((unsigned)a.v - (unsigned)b.v)); }
 __device__ __forceinline__ fx32 operator-(fx32 a) { return fx32::raw((int)(0u - (unsigned)a.v)); }
+// round(a k / 2^29) with ties away from zero = floor((a k + 2^28 - [a k < 0]) / 2^29):
+// one 64-bit multiply-add and a funnel shift
 __device__ __forceinline__ fx32 operator*(fx32 a, fx32 k) {
-    const long long p = (long long)a.v * k.v;
-    const long long m = ((p < 0 ? -p : p) + (1ll << 28)) >> 29;
-    return fx32::raw((int)(unsigned)(p < 0 ? -m : m));
+    const long long bias = (1ll << 28) + ((a.v ^ k.v) >> 31);
+    return fx32::raw((int)(unsigned)(((long long)a.v * k.v + bias) >> 29));
 }
 
 // aligned to its full size, so that LDS and global accesses of one complex
