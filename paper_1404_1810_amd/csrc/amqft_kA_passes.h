@@ -696,6 +696,48 @@ __device__ __forceinline__ cx<R> row_shift(cx<R> v) {
     return cx<R>{dpp_mov<CTRL>(v.re), dpp_mov<CTRL>(v.im)};
 }
 
+// the value of lane l (the same l in every lane), in every lane
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ fx32 lane_value(fx32 v, int l) { return fx32::raw(__builtin_amdgcn_readlane(v.v, l)); }
+template <typename R>
+__device__ __forceinline__ cx<R> lane_value_c(cx<R> v, int l) {
+    return cx<R>{lane_value(v.re, l), lane_value(v.im, l)};
+}
+
+// a of i <= 0, b of 1, c of 2, d of 3 (per lane, from values: no array
+// indexed at run time)
+template <typename R>
+__device__ __forceinline__ cx<R> pick4(cx<R> a, cx<R> b, cx<R> c, cx<R> d, int i) {
+    const R re = i <= 0 ? a.re : i == 1 ? b.re : i == 2 ? c.re : d.re;
+    const R im = i <= 0 ? a.im : i == 1 ? b.im : i == 2 ? c.im : d.im;
+    return cx<R>{re, im};
+}
+
+// Carry of a segment longer than a row of 16 lanes (aligned to rows): the
+// sum of the totals of the k rows before (ASC) / after this lane's row in its
+// segment, ((T3 + T2) + T1) nearest row last; a row's total is `inc` at its
+// last (ASC) / first lane.  Every lane of the wave must call it.
+template <bool ASC, typename R>
+__device__ __forceinline__ cx<R> rows_carry(cx<R> inc, int k) {
+    const cx<R> T0 = lane_value_c(inc, ASC ? 15 : 0), T1 = lane_value_c(inc, ASC ? 31 : 16);
+    const cx<R> T2 = lane_value_c(inc, ASC ? 47 : 32), T3 = lane_value_c(inc, ASC ? 63 : 48);
+    const int r = (threadIdx.x >> 4) & 3;
+    constexpr int d = ASC ? -1 : 1;
+    const cx<R> p1 = pick4(T0, T1, T2, T3, r + d), p2 = pick4(T0, T1, T2, T3, r + 2 * d);
+    const cx<R> p3 = pick4(T0, T1, T2, T3, r + 3 * d);
+    cx<R> c = k >= 3 ? p3 + p2 : p2;
+    c = k >= 2 ? c + p1 : p1;
+    return k >= 1 ? c : zero<R>();
+}
+
 // lane i receives lane i - d (UP) or i + d; ROW: every use stays inside
 // aligned rows of 16 lanes (then d <= 15 moves with DPP)
 template <bool UP, bool ROW, int d, typename R>
@@ -719,6 +761,21 @@ template <bool ASC, int MAXL, typename R>
 __device__ __forceinline__ cx<R> seg_excl(cx<R> t, int pos, int nl) {
     constexpr bool ROW = MAXL <= 16;
     const cx<R> z = zero<R>();
+    if constexpr (!ROW) {
+        // segments longer than a row are aligned to rows: an inclusive scan
+        // inside each row (DPP), shifted by one lane, plus the totals of the
+        // segment's earlier (later) rows read from their lanes -- no LDS
+        const int ip = pos & 15, lim = nl < 16 ? nl : 16;
+        cx<R> inc = t;
+        sfor<0, 4>([&](auto kc) {
+            constexpr int d = 1 << decltype(kc)::value;
+            const cx<R> u = row_shift<ASC, d, R>(inc);
+            if (ASC ? ip >= d : ip + d < lim) inc = inc + u;
+        });
+        const cx<R> s1 = row_shift<ASC, 1, R>(inc);
+        const cx<R> ex = (ASC ? ip >= 1 : ip + 1 < lim) ? s1 : z;
+        return rows_carry<ASC, R>(inc, ASC ? pos >> 4 : (nl - 1 - pos) >> 4) + ex;
+    }
     const cx<R> s1 = lane_shift<ASC, ROW, 1, R>(t);
     cx<R> w = (ASC ? pos >= 1 : pos + 1 < nl) ? s1 : z;
     sfor<0, ilog2c(MAXL)>([&](auto kc) {
@@ -738,11 +795,26 @@ template <bool ASC, int MAXL, typename R>
 __device__ __forceinline__ void pair_excl(cx<R> u, int pos, int nl, cx<R>& carry, cx<R>& own) {
     constexpr bool ROW = MAXL <= 16;
     const cx<R> z = zero<R>();
-    const cx<R> up = lane_shift<true, ROW, 1, R>(u), dn = lane_shift<false, ROW, 1, R>(u);
+    // a pair never crosses a row: its partner moves with DPP in every case
+    const cx<R> up = row_shift<true, 1, R>(u), dn = row_shift<false, 1, R>(u);
     const bool odd = pos & 1, paired = nl > 1;
     const cx<R> ps = !paired ? u : odd ? up + u : u + dn;  // u(2m) + u(2m+1)
     own = paired && (ASC ? odd : !odd) ? ps : u;
     const int pm = pos >> 1, np = paired ? nl >> 1 : 1;
+    if constexpr (!ROW) {
+        // as seg_excl over the pairs (8 to a row); both lanes of a pair hold its sums
+        const int ipm = pm & 7, plim = np < 8 ? np : 8;
+        cx<R> inc = ps;
+        sfor<0, 3>([&](auto kc) {
+            constexpr int d = 1 << decltype(kc)::value;
+            const cx<R> a = row_shift<ASC, 2 * d, R>(inc);
+            if (ASC ? ipm >= d : ipm + d < plim) inc = inc + a;
+        });
+        const cx<R> s2 = row_shift<ASC, 2, R>(inc);
+        const cx<R> ex = (ASC ? ipm >= 1 : ipm + 1 < plim) ? s2 : z;
+        carry = rows_carry<ASC, R>(inc, ASC ? pm >> 3 : (np - 1 - pm) >> 3) + ex;
+        return;
+    }
     const cx<R> a2 = lane_shift<ASC, ROW, 2, R>(ps);
     cx<R> w = (ASC ? pm >= 1 : pm + 1 < np) ? a2 : z;
     sfor<0, (ilog2c(MAXL) > 1 ? ilog2c(MAXL) - 1 : 0)>([&](auto kc) {

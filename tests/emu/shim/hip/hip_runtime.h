@@ -263,6 +263,7 @@ template <typename T> inline T __shfl_xor(T v, int m) {
 #define __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, aux) ::emu::buf_store<::emu::u32x2>(v, r, vo, so)
 #define __builtin_amdgcn_raw_buffer_store_b128(v, r, vo, so, aux) ::emu::buf_store<::emu::u32x4>(v, r, vo, so)
 #define __builtin_amdgcn_readfirstlane(x) (x)
+#define __builtin_amdgcn_readlane(x, l) ::emu::wave_move<int>((int)(x), [&](int) { return (int)(l); })
 #define __builtin_amdgcn_wave_barrier() ::emu::wave_barrier()
 #define __builtin_amdgcn_fence(order, scope) ((void)0)
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) ::emu::update_dpp(old, src, ctrl, rm, bm, bc)
