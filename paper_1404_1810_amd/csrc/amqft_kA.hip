@@ -559,8 +559,16 @@ __global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage
     constexpr int NG = 34, NWIN = 7, WS = NG * 8, NW = D - 5;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<R>(*blk)[NWIN * WS] = reinterpret_cast<cx<R>(*)[NWIN * WS]>(smem);  // [side][slot]
-    const int K = blockIdx.x * 256, tid = threadIdx.x;
-    const long long sl = blockIdx.y, gs = sig0 + sl;
+    // Every workgroup of a signal reads the signal's blocks >= 3 (ws2) at
+    // folded indices.  Workgroups are dealt to the eight XCDs (each with its
+    // own L2) round-robin by launch order, so the launch order is remapped to
+    // put all of a signal's workgroups on one XCD: ws2 then comes from HBM
+    // once per signal rather than once per XCD.
+    const unsigned gx = gridDim.x, total = gx * gridDim.y;
+    unsigned lid = blockIdx.x + blockIdx.y * gx;
+    if (total % 8 == 0) lid = (lid % 8) * (total / 8) + lid / 8;
+    const int K = (int)(lid % gx) * 256, tid = threadIdx.x;
+    const long long sl = lid / gx, gs = sig0 + sl;
     if (gs >= batch) return;
     // first group of window r (block 0: r = 0..3, block 1: r = 4, 5, block 2: r = 6)
     auto wg0 = [&](int r) {

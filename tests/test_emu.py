@@ -47,6 +47,7 @@ CASES = [
     ("tkernel", 7, 0, 12, 1, 1),
     ("large", 4, 0, 11, 2, 0),   # top / rows / back / bchain, rows sharing workgroups
     ("large", 8, 0, 12, 1, 1),
+    ("large", 4, 0, 11, 16, 1),  # 16 chain workgroups: the XCD remap of bchain permutes them
     ("generic", 3, 0, 10, 3, 0),  # level engine
     ("lds", 7, 0, 12, 1, 0),     # amqft_fast_kernel
 ]
