@@ -419,10 +419,10 @@ def bench_grad(args, stream):
 
 
 def bench_precision(args, stream):
-    """1024 x N=2^20, FP16 (and BF16) storage of U[-1,1) entries (seed 0), FP32
-    arithmetic, on-the-fly constants, all 8 variants: time and GB/s per variant,
-    relative L2 error against the FP64 oracle on the same stored input for a
-    few sampled signals."""
+    """1024 x N=2^20, FP16 and BF16 storage of U[-1,1) entries (seed 0; BF16:
+    the FP16 values rounded to BF16), FP32 arithmetic, on-the-fly constants,
+    all 8 variants: time and GB/s per variant, relative L2 error against the
+    FP64 oracle on the same stored input for a few sampled signals."""
     import numpy as np
     import torch
 
@@ -437,26 +437,37 @@ def bench_precision(args, stream):
         xh[s0:s0 + m].copy_(torch.from_numpy(inputs.cfg_fp16_rows(m, n, start=s0)))
         if (s0 // 8) % 32 == 31:
             log("precision inputs: %d of %d signals resident (%.0f s)" % (s0 + m, B, time.time() - t0))
-    yh = torch.empty_like(xh)
     sample = [0, B // 2, B - 1][: min(3, B)]
-    xs = xh[sample].float().cpu().numpy()
-    xs = xs[..., 0].astype(np.float64) + 1j * xs[..., 1].astype(np.float64)
-    ref = oracle.cdft(xs, 2)  # FP64 truth on the stored (quantised) input
-    res = {}
-    for v in range(1, 9):
-        plan = api.Plan(n, B, v, _lib.C32H, _lib.FLAG_ONTHEFLY_CONSTANTS)
-        r = time_launches(lambda: plan.exec(xh, out=yh), max(3, min(20, args.steps // 10)), 2, stream, floor=False)
-        got = yh[sample].float().cpu().numpy()
-        got = got[..., 0].astype(np.float64) + 1j * got[..., 1].astype(np.float64)
-        nonfinite = int((~np.isfinite(got)).sum())
-        res[str(v)] = {"kernel": plan.describe(), "avg_ms": round(r["avg_ms"], 3),
-                       "hbm_gbs": round(B * n * 8.0 / r["avg_ms"] / 1e6, 1),
-                       "rel_l2_vs_fp64_oracle": _rel(got, ref) if nonfinite == 0 else None,
-                       "nonfinite_outputs": nonfinite}
-        log("precision variant %d: %.3f ms, rel L2 %s" % (v, r["avg_ms"], res[str(v)]["rel_l2_vs_fp64_oracle"]))
-        plan.close()
-    return {"workload": "batch %d x N=2^20, fp16 storage, re/im U[-1,1) seed 0, fp32 arithmetic, "
-                        "on-the-fly constants" % B, "sampled_signals": sample, "variants": res}
+    out = {}
+    for kind, dt, code in (("fp16", torch.float16, _lib.C32H), ("bf16", torch.bfloat16, _lib.C32B)):
+        x = xh if dt == torch.float16 else xh.to(dt)
+        y = torch.empty_like(x)
+        xs = x[sample].float().cpu().numpy()
+        xs = xs[..., 0].astype(np.float64) + 1j * xs[..., 1].astype(np.float64)
+        ref = oracle.cdft(xs, 2)  # FP64 truth on the stored (quantised) input
+        res = {}
+        for v in range(1, 9):
+            plan = api.Plan(n, B, v, code, _lib.FLAG_ONTHEFLY_CONSTANTS)
+            r = time_launches(lambda: plan.exec(x, out=y), max(3, min(20, args.steps // 10)), 2, stream,
+                              floor=False)
+            got = y[sample].float().cpu().numpy()
+            got = got[..., 0].astype(np.float64) + 1j * got[..., 1].astype(np.float64)
+            nonfinite = int((~np.isfinite(got)).sum())
+            res[str(v)] = {"kernel": plan.describe(), "avg_ms": round(r["avg_ms"], 3),
+                           "hbm_gbs": round(B * n * 8.0 / r["avg_ms"] / 1e6, 1),
+                           "rel_l2_vs_fp64_oracle": _rel(got, ref) if nonfinite == 0 else None,
+                           "nonfinite_outputs": nonfinite}
+            log("precision %s variant %d: %.3f ms, rel L2 %s" % (kind, v, r["avg_ms"],
+                                                                  res[str(v)]["rel_l2_vs_fp64_oracle"]))
+            plan.close()
+        out[kind] = res
+        del y
+        if x is not xh:
+            del x
+        torch.cuda.empty_cache()
+    return {"workload": "batch %d x N=2^20, fp16 storage (and the same values rounded to bf16), re/im U[-1,1) "
+                        "seed 0, fp32 arithmetic, on-the-fly constants" % B, "sampled_signals": sample,
+            "variants": out}
 
 
 def bench_fixed(args, stream):
@@ -532,8 +543,8 @@ def main():
     if args.workload == "precision":
         stream = torch.cuda.current_stream()
         res = bench_precision(args, stream)
-        print(json.dumps({"metric": "fp16-storage AM-QFT: GB/s and relative L2 error per variant, N=2^20",
-                          "n_gpus": 1, "data": "synthetic", "dtype": "f16 storage, f32 arithmetic",
+        print(json.dumps({"metric": "fp16 / bf16-storage AM-QFT: GB/s and relative L2 error per variant, N=2^20",
+                          "n_gpus": 1, "data": "synthetic", "dtype": "f16 / bf16 storage, f32 arithmetic",
                           "config": {"workload": res["workload"]}, "variants": res["variants"],
                           "sampled_signals": res["sampled_signals"]}), flush=True)
         return
