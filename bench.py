@@ -31,7 +31,7 @@ CSRC = os.path.join(ROOT, "paper_1404_1810_amd", "csrc")
 # only for the exact sources it was taken on)
 KERNEL_SOURCES = {
     "amqft_kA_kernel": ["amqft_kA.hip", "amqft_kA_passes.h", "amqft_leaf.h", "amqft_device.h"],
-    "amqft_kB_kernel": ["amqft_kB.hip", "amqft_kA_passes.h", "amqft_leaf.h", "amqft_device.h"],
+    "amqft_kB_kernel": ["amqft_kB.hip", "amqft_kB_passes.h", "amqft_kA_passes.h", "amqft_leaf.h", "amqft_device.h"],
     "amqft_fast_kernel": ["amqft_fast.hip", "amqft_levels.h", "amqft_leaf.h", "amqft_device.h"],
     "amqft_lds_kernel": ["amqft_lds.hip", "amqft_levels.h", "amqft_device.h"],
 }

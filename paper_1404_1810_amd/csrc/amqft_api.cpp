@@ -843,10 +843,11 @@ amqft_status amqft_plan_describe(amqft_plan p, char* buf, size_t len) {
         snprintf(buf, len, "many-length plan: %lld signals, persistent kernel grid=%d items=%d, %d long-length classes",
                  (long long)p->count, p->grid, p->nitems, nclass);
     } else if (p->large) {
-        snprintf(buf, len, p->logn >= 18 ? "amqft_kL_{top,rtop,rows,rback,back,bchain}<%d> n=%lld chunk=%lld"
-                                         : "amqft_kL_{top,rows,back,bchain}<%d> n=%lld chunk=%lld",
-                 p->variant, (long long)p->n,
-                 (long long)p->chunk);
+        const bool transposed = p->variant == 2 || p->variant == 6;
+        snprintf(buf, len, transposed       ? "amqft_kLT_{c0,fold,b0,rows,top}<%d> n=%lld chunk=%lld"
+                           : p->logn >= 18 ? "amqft_kL_{top,rtop,rows,rback,back,bchain}<%d> n=%lld chunk=%lld"
+                                           : "amqft_kL_{top,rows,back,bchain}<%d> n=%lld chunk=%lld",
+                 p->variant, (long long)p->n, (long long)p->chunk);
     } else if (p->multipass) {
         snprintf(buf, len, "multi-pass engine n=%lld sb=%d chunk=%lld", (long long)p->n, p->sb, (long long)p->chunk);
     } else {

@@ -106,6 +106,13 @@ struct kl_launch {
     const void* offsets = nullptr;
 };
 bool kL_supported(int variant, int logn, int dtype);
+// variants 2 and 6 on the transposed program of that path (amqft_kLT.hip):
+// N = 2^15 .. 2^17 (FP64 2^14 .. 2^16), forced from 2^11; kL_* below
+// dispatch to these for those variants
+bool kLT_supported(int variant, int logn, int dtype);
+bool kLT_supported_forced(int variant, int logn, int dtype);
+hipError_t prime_kLT(int variant, int dtype);
+hipError_t launch_kLT(const kl_launch& a, hipStream_t stream);
 // sizes a plan may force onto that path (from 2^11; tests)
 bool kL_supported_forced(int variant, int logn, int dtype);
 size_t kL_ws_bytes_per_signal(int logn, int dtype);

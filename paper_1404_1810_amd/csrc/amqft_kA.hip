@@ -863,12 +863,14 @@ hipError_t launch_kA_loss(const loss_launch& a, hipStream_t st) {
 }
 
 bool kL_supported(int variant, int logn, int dtype) {
+    if (variant == 2 || variant == 6) return kLT_supported(variant, logn, dtype);
     if (variant != 4 && variant != 8) return false;
     if (dtype == 0) return logn >= 14 && logn <= 16;
     return logn >= 15 && logn <= 20;  // FP32 arithmetic: FP32, FP16 and BF16 storage
 }
 
 bool kL_supported_forced(int variant, int logn, int dtype) {
+    if (variant == 2 || variant == 6) return kLT_supported_forced(variant, logn, dtype);
     if (variant != 4 && variant != 8) return false;
     if (dtype == 0) return logn >= 11 && logn <= 16;
     if (dtype == 1) return logn >= 11 && logn <= 20;
@@ -878,6 +880,7 @@ bool kL_supported_forced(int variant, int logn, int dtype) {
 size_t kL_ws_bytes_per_signal(int logn, int dtype) { return ((size_t)1 << logn) * (dtype == 0 ? 16 : 8); }
 
 hipError_t prime_kL(int variant, int dtype) {
+    if (variant == 2 || variant == 6) return prime_kLT(variant, dtype);
     // the rows kernels depend on the arithmetic type only (float for dtypes 1..3)
     if (variant == 4) return dtype == 0 ? prime_kL_n<4, double, 11, 16>() : prime_kL_n<4, float, 11, 20>();
     if (variant == 8) return dtype == 0 ? prime_kL_n<8, double, 11, 16>() : prime_kL_n<8, float, 11, 20>();
@@ -896,6 +899,7 @@ static hipError_t launch_kL_t(const kl_launch& a, hipStream_t st) {
 
 hipError_t launch_kL(const kl_launch& a, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
+    if (a.variant == 2 || a.variant == 6) return launch_kLT(a, st);
     if (a.variant == 4) return launch_kL_t<4>(a, st);
     return launch_kL_t<8>(a, st);
 }

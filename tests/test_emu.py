@@ -48,6 +48,10 @@ CASES = [
     ("large", 4, 0, 11, 2, 0),   # top / rows / back / bchain, rows sharing workgroups
     ("large", 8, 0, 12, 1, 1),
     ("large", 4, 0, 11, 16, 1),  # 16 chain workgroups: the XCD remap of bchain permutes them
+    ("large", 2, 0, 11, 3, 0),   # transposed large path (c0 / fold / b0 / rows / top), rows sharing workgroups
+    ("large", 6, 0, 12, 2, 1),
+    ("large", 2, 1, 12, 2, 0),
+    ("large", 2, 0, 13, 1, 1),   # two-walk fold, 4096-point rows
     ("generic", 3, 0, 10, 3, 0),  # level engine
     ("lds", 7, 0, 12, 1, 0),     # amqft_fast_kernel
 ]
@@ -73,11 +77,13 @@ def test_kernel_source_on_cpu(emu_exe, tmp_path, path, variant, dtype, logn, bat
     assert rel(y, ref) <= b, (rel(y, ref), b)
 
 
-@pytest.mark.parametrize("vb,logn", [(2, 12), (6, 9), (2, 8), (6, 8)])
-def test_transposed_program_is_the_dual_variant(emu_exe, tmp_path, vb, logn):
+@pytest.mark.parametrize("path,vb,logn", [("tkernel", 2, 12), ("tkernel", 6, 9), ("tkernel", 2, 8), ("tkernel", 6, 8),
+                                          ("large", 2, 12), ("large", 6, 11)])
+def test_transposed_program_is_the_dual_variant(emu_exe, tmp_path, path, vb, logn):
     """The duality of the paper's M steps (M4^T = M2, M8^T = M6; skeleton A
     <-> B): the transposed program of the skeleton-A kernel of variant 4 (8),
-    run without FMA contraction, reproduces the oracle's FP32 build of
+    and of its large-N path, run without FMA contraction, reproduces the
+    oracle's FP32 build of
     variant 2 (6) bit for bit -- including variant 6's ill-conditioned
     rounding, which differs from variant 8's by more than the error itself."""
     import oracle
@@ -85,7 +91,7 @@ def test_transposed_program_is_the_dual_variant(emu_exe, tmp_path, vb, logn):
     x = inputs.complex_normal(31 + logn, batch, n).astype(np.complex64)
     fin, fout = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
     x.tofile(fin)
-    r = subprocess.run([emu_exe, "tkernel", str(vb), "1", str(logn), str(batch), "0", fin, fout],
+    r = subprocess.run([emu_exe, path, str(vb), "1", str(logn), str(batch), "0", fin, fout],
                        capture_output=True, text=True, timeout=300,
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1"))
     assert r.returncode == 0, r.stderr[-4000:]

@@ -258,14 +258,15 @@ def _large_case(api, _lib, variant, dtype, n, batch, flags_extra, want_chunk=Non
 @pytest.mark.parametrize("dtype,n,batch,chunk", (("c64", 1 << 15, 5, 4), ("c64", 1 << 17, 3, 1),
                                                  ("c128", 1 << 14, 5, 4), ("c128", 1 << 15, 3, 2),
                                                  ("c128", 1 << 16, 2, 1)))
-@pytest.mark.parametrize("variant", [4, 8])
+@pytest.mark.parametrize("variant", [4, 8, 2, 6])
 def test_large_path(variant, dtype, n, batch, chunk, monkeypatch):
     """The four-kernel path for N above one workgroup's LDS (variants 4 and 8:
-    2^15 .. 2^17 FP32, 2^14 .. 2^16 FP64), its workspaces cut to 1 MiB so that
+    2^15 .. 2^17 FP32, 2^14 .. 2^16 FP64) and its transposed program (the
+    five kernels of variants 2 and 6), workspaces cut to 1 MiB so that
     every batch runs in several chunks with a ragged last one; forward with the
-    table and with on-the-fly constants, adjoint, in place.  Variant 8 has no
-    pin at these sizes (its own FP64 error is above 1e-3 from 2^13); its
-    kernels are pinned by test_large_path_forced."""
+    table and with on-the-fly constants, adjoint, in place.  Variants 6 and 8
+    have no pin at these sizes (their own FP64 error is above 1e-3 from 2^13);
+    their kernels are pinned by test_large_path_forced."""
     api = _api()
     from paper_1404_1810_amd import _lib
     monkeypatch.setenv("AMQFT_LARGE_WS_MB", "1")
@@ -279,13 +280,14 @@ LARGE_FORCED = (("c128", 1 << 11, 5), ("c128", 1 << 12, 3), ("c128", 1 << 13, 2)
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("dtype,n,batch", LARGE_FORCED)
-@pytest.mark.parametrize("variant", [4, 8])
+@pytest.mark.parametrize("variant", [4, 8, 2, 6])
 def test_large_path_forced(variant, dtype, n, batch, monkeypatch):
-    """The same four kernels (top, rows, back, bchain) forced at N = 2^11 ..
-    2^14, where the rows are 2^8 .. 2^11-point transforms that share a
-    workgroup.  At FP64 2^11 and 2^12 every kernel of variant 8 is pinned at
-    20x its own FP64 error (<= 5e-5); forward with table and on-the-fly
-    constants, adjoint in place, chunks of 1 MiB of workspace."""
+    """The same kernels (top, rows, back, bchain; for 2 and 6 c0, fold, b0,
+    rows, top) forced at N = 2^11 .. 2^14, where the rows are 2^8 .. 2^11-point
+    transforms that share a workgroup.  At FP64 2^11 and 2^12 every kernel of
+    variants 8 and 6 is pinned at 20x its own FP64 error (<= 5e-5); forward with
+    table and on-the-fly constants, adjoint in place, chunks of 1 MiB of
+    workspace."""
     api = _api()
     from paper_1404_1810_amd import _lib
     monkeypatch.setenv("AMQFT_LARGE_WS_MB", "1")

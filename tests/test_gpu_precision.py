@@ -94,7 +94,7 @@ def test_n2p20_sampled(variant, kind):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("variant", [4, 8])
+@pytest.mark.parametrize("variant", [4, 8, 2, 6])
 def test_reduced_storage_large_path(variant, monkeypatch):
     """FP16 and BF16 storage on the four-kernel path (N above one workgroup's
     LDS), workspaces cut to 1 MiB so that the batch runs in chunks."""
