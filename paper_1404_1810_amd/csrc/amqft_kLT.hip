@@ -102,20 +102,43 @@ __global__ __launch_bounds__(fold_threads<LOGN>()) void amqft_kLT_fold(cx<R>* __
 // ---------------------------------------------------------------------------
 // b0: B0^T for position p of the depth-3 block layout (block a, index j): the
 // window of depth-0 runs of 8 that the time-side M2 / M6 terms reach, three
-// transposed levels per side, child q -> row (side, q) at p
+// transposed levels per side, child q -> row (side, q) at p.  Run j of
+// depth-0 block a starts at 8p (depth-0 blocks sit at H - H / 2^a = 8 (W3 -
+// W3 / 2^a)), so the 256 positions of a workgroup read one contiguous range
+// of 8 (256 + 2) values per side: staged in LDS with coalesced loads, one pad
+// slot per run of 8 against bank conflicts.
 // ---------------------------------------------------------------------------
+constexpr int kB0Pos = 256;                      // depth-3 positions per workgroup
+constexpr int kB0Runs = kB0Pos + 2;              // with one run before and after
+__device__ __forceinline__ int b0_slot(int i) { return i + (i >> 3); }
+template <typename R>
+constexpr size_t kLT_b0_lds() { return 2 * (size_t)(9 * kB0Runs) * sizeof(cx<R>); }
+
 template <int VB, typename R, int LOGN>
-__global__ __launch_bounds__(256) void amqft_kLT_b0(const cx<R>* __restrict__ ws2, cx<R>* __restrict__ ws1) {
+__global__ __launch_bounds__(kB0Pos) void amqft_kLT_b0(const cx<R>* __restrict__ ws2, cx<R>* __restrict__ ws1) {
     constexpr int VA = transposed_of<VB>::V;
-    constexpr int N = 1 << LOGN, H = N / 2, W3 = N / 16, LW3 = ilog2c(W3);
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    constexpr int N = 1 << LOGN, H = N / 2, W3 = N / 16, LW3 = ilog2c(W3), RS = 9 * kB0Runs;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<R>* st = reinterpret_cast<cx<R>*>(smem);  // [side][b0_slot(depth-0 position - 8 (p0 - 1))]
+    const int p0 = blockIdx.x * kB0Pos, tid = threadIdx.x;
+    const cx<R>* g = ws2 + (long long)blockIdx.y * N;
+    cx<R>* rows = ws1 + (long long)blockIdx.y * N;
+    const int lo = 8 * (p0 - 1);
+    for (int i = tid; i < 8 * kB0Runs; i += kB0Pos) {
+        const int d0 = lo + i;
+        const bool in = d0 >= 0 && d0 < H;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const cx<R> v = g[side * H + (in ? d0 : 0)];
+            stc(st + side * RS + b0_slot(i), in ? v : zero<R>());
+        }
+    }
+    __syncthreads();
+    const int p = p0 + tid;
     if (p >= W3 - 1) return;
     const int a = __clz(~(p << (32 - LW3)));
     const int j = p - (W3 - (W3 >> a));
     const int sp = W3 >> (a + 1);
-    const cx<R>* g = ws2 + (long long)blockIdx.y * N;
-    cx<R>* rows = ws1 + (long long)blockIdx.y * N;
-    const int b0 = H - (H >> a);  // depth-0 block a of side 0
     sfor<0, 2>([&](auto sc) {
         constexpr int side = decltype(sc)::value;
         using WW = halo_window<VA, side>;
@@ -123,11 +146,11 @@ __global__ __launch_bounds__(256) void amqft_kLT_b0(const cx<R>* __restrict__ ws
 #pragma unroll
         for (int d = 0; d < WW::W; ++d) {
             const int jj = j + WW::OFF + d;
-            const bool in = jj >= 0 && jj < sp;
-            const cx<R>* run = g + side * H + b0 + 8 * (in ? jj : j);
+            const bool in = jj >= 0 && jj < sp;  // runs outside block a count as zero
+            const int r0 = 8 * (tid + 1 + WW::OFF + d);  // the run's first value in the staged range
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const cx<R> v = run[e];
+                const cx<R> v = ldc(st + side * RS + b0_slot(r0 + e));
                 cur[0][8 * d + e] = in ? v : zero<R>();
             }
         }
@@ -164,17 +187,13 @@ __global__ __launch_bounds__(kgeo<LOGN - 3>::WG) void amqft_kLT_rows(cx<R>* __re
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) row[hh] = sig + ((hh ^ (SW ? par(P) : 0)) * 8 + P) * W3;
     // the row's block layout into LDS; the blocks of 4, 2 and 1 points (the
-    // last seven slots) stay in registers of the thread m0 = 0
+    // last seven slots of each row) into the chain slots, which no pass of a
+    // row touches (keeping them in registers would cost occupancy)
+    using L = lds_layout<LR>;
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh)
         for (int pos = m0; pos < W3 - 8; pos += G::T) stc(w + hh * G::HS + pad(pos), row[hh][pos]);
-    cx<R> small[2][7];
-    if (m0 == 0) {
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-            for (int i = 0; i < 7; ++i) small[hh][i] = row[hh][W3 - 8 + i];
-    }
+    if (m0 < 14) stc(w + L::chain(m0), row[m0 / 7][W3 - 8 + m0 % 7]);
     fill_constants<VA, LR, R>(kt, kf, ktab, 3, false, tid);
     __syncthreads();
     b0T_pass<VA, LR, R>(wall, tid);
@@ -199,8 +218,11 @@ __global__ __launch_bounds__(kgeo<LOGN - 3>::WG) void amqft_kLT_rows(cx<R>* __re
         // the transposes of the row's blocks of 4, 2 and 1 points
         sfor<0, 2>([&](auto hc) {
             constexpr int hh = decltype(hc)::value;
-            cx<R> b4[4] = {small[hh][0], small[hh][1], small[hh][2], small[hh][3]};
-            cx<R> b2[2] = {small[hh][4], small[hh][5]};
+            cx<R> small[7];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) small[i] = ldc(w + L::chain(7 * hh + i));
+            cx<R> b4[4] = {small[0], small[1], small[2], small[3]};
+            cx<R> b2[2] = {small[4], small[5]};
             leaf::to<VB, 4, hh, R>(b4, kt, G::D);
             leaf::to<VB, 2, hh, R>(b2, kt, G::D);
             row[hh][(W3 / 8) * 1] = b4[0];
@@ -209,7 +231,7 @@ __global__ __launch_bounds__(kgeo<LOGN - 3>::WG) void amqft_kLT_rows(cx<R>* __re
             row[hh][(W3 / 8) * 7] = b4[3];
             row[hh][(W3 / 8) * 2] = b2[0];
             row[hh][(W3 / 8) * 6] = b2[1];
-            row[hh][(W3 / 8) * 4] = small[hh][6];
+            row[hh][(W3 / 8) * 4] = small[6];
         });
     }
 }
@@ -267,8 +289,8 @@ hipError_t launch_kLT_n(const kl_launch& a, hipStream_t st) {
                            s0, (long long)a.batch, flags, static_cast<const long long*>(a.offsets));
         hipLaunchKernelGGL((amqft_kLT_fold<R, LOGN>), dim3((unsigned)nb), dim3(fold_threads<LOGN>()), lds_fold, st, ws2,
                            wsc);
-        hipLaunchKernelGGL((amqft_kLT_b0<VB, R, LOGN>), dim3((W3 - 1 + 255) / 256, (unsigned)nb), dim3(256), 0, st,
-                           static_cast<const cx<R>*>(ws2), ws1);
+        hipLaunchKernelGGL((amqft_kLT_b0<VB, R, LOGN>), dim3((W3 - 1 + kB0Pos - 1) / kB0Pos, (unsigned)nb), dim3(kB0Pos),
+                           kLT_b0_lds<R>(), st, static_cast<const cx<R>*>(ws2), ws1);
         hipLaunchKernelGGL((amqft_kLT_rows<VB, R, LOGN>), dim3(8 / GR::SPW, (unsigned)nb), dim3(GR::WG), lds_rows, st,
                            ws1, kt);
         hipLaunchKernelGGL((amqft_kLT_top<VB, S, LOGN>), gw, dim3(256), 0, st, static_cast<const cx<R>*>(ws1),
@@ -309,6 +331,9 @@ hipError_t prime_kLT_n() {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e == hipSuccess)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kLT_fold<R, LOGN>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kLT_b0<VB, R, LOGN>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if constexpr (LOGN < LMAX) {
         if (e == hipSuccess) e = prime_kLT_n<VB, R, LOGN + 1, LMAX>();
