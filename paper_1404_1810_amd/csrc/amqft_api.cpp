@@ -844,7 +844,8 @@ amqft_status amqft_plan_describe(amqft_plan p, char* buf, size_t len) {
                  (long long)p->count, p->grid, p->nitems, nclass);
     } else if (p->large) {
         const bool transposed = p->variant == 2 || p->variant == 6;
-        snprintf(buf, len, transposed       ? "amqft_kLT_{c0,fold,b0,rows,top}<%d> n=%lld chunk=%lld"
+        snprintf(buf, len, transposed       ? (p->logn >= 18 ? "amqft_kLT_{c0,fold,b0,rback,rows,rtop,top}<%d> n=%lld chunk=%lld"
+                                                             : "amqft_kLT_{c0,fold,b0,rows,top}<%d> n=%lld chunk=%lld")
                            : p->logn >= 18 ? "amqft_kL_{top,rtop,rows,rback,back,bchain}<%d> n=%lld chunk=%lld"
                                            : "amqft_kL_{top,rows,back,bchain}<%d> n=%lld chunk=%lld",
                  p->variant, (long long)p->n, (long long)p->chunk);

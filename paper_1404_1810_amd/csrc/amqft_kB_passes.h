@@ -281,13 +281,16 @@ struct fold_walk {
 
     // the orbit's values of the level LS; slots a lane's orbit lacks (S(0),
     // and v[2 M0] outside the DCT orbit 0) read a position of its own orbit
-    static __device__ __forceinline__ void load(const cx<R>* w, bool dst, int r, cx<R> (&v)[NV]) {
+    // (wc: the base of the chain slots)
+    static __device__ __forceinline__ void load(const cx<R>* w, const cx<R>* wc, bool dst, int r, cx<R> (&v)[NV]) {
 #pragma unroll
         for (int i = 0; i < 2 * M0; ++i) v[i] = ldc(w + pos<LS>(dst, kpos(i, r) + (dst && i == 0 && r == 0 ? P / 2 : 0)));
-        v[2 * M0] = ldc(w + (!dst && r == 0 ? LAY::ch(8) : pos<LS>(dst, kpos(1, r))));
+        v[2 * M0] = !dst && r == 0 ? ldc(wc + LAY::ch(8)) : ldc(w + pos<LS>(dst, kpos(1, r)));
     }
 
-    static __device__ __forceinline__ void walk(cx<R>* w, bool dst, int r, cx<R> (&v)[NV]) {
+    // block entries go to w, the values of the level P / 2 to wo (the same
+    // positions), the top and the last level's chain values to wc
+    static __device__ __forceinline__ void walk(cx<R>* w, cx<R>* wo, cx<R>* wc, bool dst, int r, cx<R> (&v)[NV]) {
         const bool o0 = r == 0;
         sfor<0, NL>([&](auto lc) {
             constexpr int Lv = LS >> decltype(lc)::value;
@@ -306,9 +309,8 @@ struct fold_walk {
             }
         });
         // v[0]: index r of the level P / 2 (none for the DST orbit 0)
-        const int o = LAST ? LAY::ch((dst ? 8 : 0) + r) : pos<P / 2>(dst, r);
-        if (!(dst && o0)) stc(w + o, v[0]);
-        if (!dst && o0) stc(w + LAY::ch(8), v[1]);
+        if (!(dst && o0)) stc(LAST ? wc + LAY::ch((dst ? 8 : 0) + r) : wo + pos<P / 2>(dst, r), v[0]);
+        if (!dst && o0) stc(wc + LAY::ch(8), v[1]);
     }
 };
 
@@ -324,9 +326,9 @@ __device__ __forceinline__ void fold_block(cx<R>* w, int tid) {
     const bool act = tid < P, dst = tid >= P / 2;
     const int r = tid & (P / 2 - 1);
     cx<R> v[F::NV];
-    if (act) F::load(w, dst, r, v);
+    if (act) F::load(w, w, dst, r, v);
     __syncthreads();  // the next level's values land where other lanes' loads were
-    if (act) F::walk(w, dst, r, v);
+    if (act) F::walk(w, w, w, dst, r, v);
     if constexpr (!F::LAST) {
         __syncthreads();
         fold_block<LOGN, NT, P / 2, R, LAY>(w, tid);
@@ -345,11 +347,11 @@ __device__ __forceinline__ void fold(cx<R>* wall, int tid) {
         const bool act = k < P1, dst = k >= P1 / 2;
         const int r = k & (P1 / 2 - 1);
         cx<R> v[F::NV];
-        if (act) F::load(w, dst, r, v);
+        if (act) F::load(w, w, dst, r, v);
         // the values of the level P1 / 2 land where other lanes' loads were
         // (the last level writes only chain slots and the lane's own orbit)
         if constexpr (!F::LAST) wave_sync();
-        if (act) F::walk(w, dst, r, v);
+        if (act) F::walk(w, w, w, dst, r, v);
     }
     if constexpr (P1 > 16) {
         using F = fold_walk<LOGN, 16, P1 / 2, R>;
@@ -357,8 +359,8 @@ __device__ __forceinline__ void fold(cx<R>* wall, int tid) {
         const bool act = k < 16, dst = k >= 8;
         const int r = k & 7;
         cx<R> v[F::NV];
-        if (act) F::load(w, dst, r, v);
-        if (act) F::walk(w, dst, r, v);
+        if (act) F::load(w, w, dst, r, v);
+        if (act) F::walk(w, w, w, dst, r, v);
     }
     __syncthreads();
 }
@@ -920,14 +922,14 @@ __device__ __forceinline__ void orbitT_pass(cx<R>* wall, const R* kt, const R* k
 // levels 2..0 backward on the orbit of m0 of a 2^LOGN-point transform (kt:
 // its constant table): d3of(side, P8) gives the depth-3 value of row P8 of a
 // side at slot m0; cd[side][] comes out in the order of F1's c / d values
-template <int VA, int LOGN, typename R, typename LD>
+template <int VA, int LOGN, typename R, int KS = 0, typename LD>
 __device__ __forceinline__ void f1T_levels(const R* kt, int m0, LD d3of, cx<R> (&cd)[2][8]) {
-    using G = kgeo<LOGN>;
     constexpr bool SW = variant_traits<VA>::switches;
-    constexpr int N8 = G::N / 8, N4 = G::N / 4;
-    const R k0[4] = {kt[m0], kt[N8 - m0], kt[N8 + m0], kt[N4 - m0]};
-    const R k1[2] = {kt[2 * m0], kt[N4 - 2 * m0]};
-    const R k2 = kt[4 * m0];
+    constexpr int N8 = (1 << LOGN) / 8, N4 = (1 << LOGN) / 4;
+    // KS: the table is that of a transform 2^KS times longer (read at stride 2^KS)
+    const R k0[4] = {kt[m0 << KS], kt[(N8 - m0) << KS], kt[(N8 + m0) << KS], kt[(N4 - m0) << KS]};
+    const R k1[2] = {kt[(2 * m0) << KS], kt[(N4 - 2 * m0) << KS]};
+    const R k2 = kt[(4 * m0) << KS];
     sfor<0, 2>([&](auto sc) {
         constexpr int side = decltype(sc)::value;
         cx<R> d3[8];

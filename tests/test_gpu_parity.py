@@ -297,12 +297,13 @@ def test_large_path_forced(variant, dtype, n, batch, monkeypatch):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("n", [1 << 18, 1 << 20])
-@pytest.mark.parametrize("variant", [4, 8])
+@pytest.mark.parametrize("variant", [4, 8, 2, 6])
 def test_large_path_deep(variant, n):
-    """N = 2^18 and 2^20 (FP32) on the six-kernel path: depth-3 rows split once
-    more into depth-6 rows; table and device-generated constants, adjoint.
-    The depth-6 kernels (rtop, rback) exist only from 2^18, where variant 8
-    has no pin: its cases are reported, not asserted."""
+    """N = 2^18 and 2^20 (FP32) on the six-kernel path (variants 4, 8) and its
+    transpose (2, 6): depth-3 rows split once more into depth-6 rows; table
+    and device-generated constants, adjoint.  The depth-6 kernels (rtop,
+    rback and their transposes) exist only from 2^18, where variants 6 and 8
+    have no pin: their cases are reported, not asserted."""
     api = _api()
     from paper_1404_1810_amd import _lib
     batch = 2 if n == 1 << 18 else 1
