@@ -505,6 +505,50 @@ def bench_fixed(args, stream):
                         "Q2.29 constants, forward" % (B, n, seed), "variants": res}
 
 
+def bench_inplace(args, stream):
+    """The large-N path in place against out of place: 256 signals of 2^16
+    points (FP32, variant 4, 512 MiB), the same inputs, default workspaces;
+    time per launch, workspace bytes, and whether the outputs agree bit for
+    bit (same operations in the same order)."""
+    import ctypes
+
+    import torch
+
+    from paper_1404_1810_amd import _lib, api, inputs
+
+    n, B, v = 1 << 16, 256, 4
+    seed = inputs.SEEDS["fp32_n4096"]
+    x = torch.empty((B, n), dtype=torch.complex64, device="cuda")
+    for s0, rows in inputs.chunks("normal", seed, B, n):
+        x[s0:s0 + len(rows)].copy_(torch.from_numpy(rows.astype("complex64")))
+    algo = B * n * 16.0
+    res = {}
+    outs = {}
+    for name, flags in (("out_of_place", 0), ("in_place", _lib.FLAG_IN_PLACE)):
+        plan = api.Plan(n, B, v, _lib.C64, flags)
+        ws = ctypes.c_size_t(0)
+        _lib.check(_lib.load().amqft_plan_workspace_size(plan.handle, ctypes.byref(ws)), "workspace")
+        if flags:
+            y = x.clone()
+            r = time_launches(lambda: plan.exec(y, out=y), args.steps // 4, args.warmup, stream)
+            y.copy_(x)
+            plan.exec(y, out=y)
+        else:
+            y = torch.empty_like(x)
+            r = time_launches(lambda: plan.exec(x, out=y), args.steps // 4, args.warmup, stream)
+        torch.cuda.synchronize()
+        outs[name] = y
+        res[name] = {"kernel": plan.describe(), "avg_ms": round(r["avg_ms"], 5),
+                     "algorithmic_gbs": round(algo / r["avg_ms"] / 1e6, 1),
+                     "workspace_bytes": int(ws.value), "workspace_over_data": round(ws.value / (B * n * 8.0), 4)}
+        log("large path %s: avg %.4f ms, %.1f GB/s algorithmic, workspace %.1f MiB"
+            % (name, r["avg_ms"], algo / r["avg_ms"] / 1e6, ws.value / 2 ** 20))
+        plan.close()
+    res["bit_identical"] = bool(torch.equal(outs["in_place"], outs["out_of_place"]))
+    return {"workload": "batch %d x N=%d complex64, re/im N(0,1) seed %d, variant %d, forward" % (B, n, seed, v),
+            **res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -646,6 +690,9 @@ def main():
         torch.cuda.empty_cache()
         log("fixed-point workload")
         extra["fixed_point"] = bench_fixed(args, stream)
+        torch.cuda.empty_cache()
+        log("in-place large-N workload")
+        extra["in_place"] = bench_inplace(args, stream)
         torch.cuda.empty_cache()
         line["workloads"] = extra
     tr = load_traffic(family, args.variant, n, batch)

@@ -20,6 +20,7 @@ FLAG_NO_AUTOTUNE = 2
 FLAG_FORCE_MULTIPASS = 4
 FLAG_FORCE_LARGE = 8
 FLAG_TRANSPOSED_ADJOINT = 16
+FLAG_IN_PLACE = 32
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 #: every function the header declares, with its ctypes signature

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libamqft.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["amqft_lds.hip", "amqft_fast.hip", "amqft_kA.hip", "amqft_kB.hip", "amqft_kLT.hip", "amqft_multipass.hip", "amqft_static.hip", "amqft_api.cpp"]
-HEADERS = ["amqft_device.h", "amqft_internal.h", "amqft_levels.h", "amqft_leaf.h", "amqft_kA_passes.h", "amqft_kB_passes.h"]
+HEADERS = ["amqft_device.h", "amqft_internal.h", "amqft_levels.h", "amqft_leaf.h", "amqft_kA_passes.h", "amqft_kB_passes.h",
+           "amqft_iplayout.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

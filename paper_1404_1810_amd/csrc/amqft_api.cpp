@@ -17,6 +17,7 @@
 #include "../../include/amqft.h"
 #include "amqft_device.h"
 #include "amqft_internal.h"
+#include "amqft_iplayout.h"
 
 using namespace amqft;
 
@@ -59,6 +60,11 @@ struct amqft_plan_s {
     int sb = 0;
     int64_t chunk = 0;
     void* ws[3] = {nullptr, nullptr, nullptr};
+    // in-place large path: shared-slot workspace and slot table (device)
+    bool inplace = false;
+    void* ws3 = nullptr;
+    int* iptab = nullptr;
+    int ipnsh = 0;
     size_t ws_bytes = 0;
     const void* offsets = nullptr;  // per-signal offsets (sub-plans of a many-length plan)
     // many-length plans
@@ -91,7 +97,7 @@ amqft_status hip_fail(hipError_t e) {
 bool valid_variant(int v) { return v >= 1 && v <= 8; }
 bool valid_dtype(int t) { return t >= 0 && t <= 4; }
 constexpr unsigned kAllFlags = AMQFT_FLAG_ONTHEFLY_CONSTANTS | AMQFT_FLAG_NO_AUTOTUNE | AMQFT_FLAG_FORCE_MULTIPASS |
-                               AMQFT_FLAG_FORCE_LARGE | AMQFT_FLAG_TRANSPOSED_ADJOINT;
+                               AMQFT_FLAG_FORCE_LARGE | AMQFT_FLAG_TRANSPOSED_ADJOINT | AMQFT_FLAG_IN_PLACE;
 
 // the variant whose program is the transpose of variant v's (skeleton A <-> B)
 int dual_variant(int v) {
@@ -276,6 +282,10 @@ amqft_status exec_single(amqft_plan p, const void* in, void* out, hipStream_t st
         k.conj_in = adjoint;
         k.conj_out = adjoint;
         k.offsets = p->offsets;
+        k.inplace = p->inplace;
+        k.ws3 = p->ws3;
+        k.iptab = p->iptab;
+        k.ipnsh = p->ipnsh;
         hipError_t e = launch_kL(k, stream);
         return e == hipSuccess ? AMQFT_OK : hip_fail(e);
     }
@@ -463,6 +473,7 @@ amqft_status exec_common(amqft_plan p, const void* in, void* out, void* stream, 
     if (!p) return AMQFT_ERR_INVALID_ARG;
     if ((p->many ? p->count : p->batch) == 0) return AMQFT_OK;  // nothing to read or write
     if (!in || !out) return AMQFT_ERR_INVALID_ARG;
+    if ((p->flags & AMQFT_FLAG_IN_PLACE) && in != out) return AMQFT_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (p->many && !p->tuned) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -498,7 +509,33 @@ amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int varian
         if (e != hipSuccess) st = hip_fail(e);
     }
     if (st != AMQFT_OK) { amqft_plan_destroy(p); return st; }
-    if (mp && !(flags & AMQFT_FLAG_FORCE_MULTIPASS) &&
+    if (mp && (flags & AMQFT_FLAG_IN_PLACE)) {
+        // the rows stay in the signal buffer; workspaces for the blocks the
+        // chain reads at folded indices, the shared slots and the chain
+        p->large = true;
+        p->inplace = true;
+        std::vector<int> tab;
+        p->ipnsh = ip_layout_build(logn, tab);
+        if (p->ipnsh < 0) { amqft_plan_destroy(p); return AMQFT_ERR_UNSUPPORTED; }
+        e = hipMalloc(&p->iptab, tab.size() * sizeof(int));
+        if (e == hipSuccess) e = hipMemcpy(p->iptab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { amqft_plan_destroy(p); return hip_fail(e); }
+        const size_t esz = dtype == AMQFT_C128 ? 16 : 8;
+        const size_t per2 = ((size_t(1) << logn) / 8 + 16) * esz, per3 = (size_t)p->ipnsh * 16 * esz, perc = 16 * esz;
+        size_t cap = size_t(128) << 20;
+        if (const char* env = getenv("AMQFT_LARGE_WS_MB")) {
+            const long mb = atol(env);
+            if (mb >= 1 && mb <= (1l << 20)) cap = size_t(mb) << 20;
+        }
+        p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per2)));
+        p->ws_bytes = (size_t)p->chunk * (per2 + per3 + perc);
+        if (batch > 0) {
+            e = hipMalloc(&p->ws[1], (size_t)p->chunk * per2);
+            if (e == hipSuccess) e = hipMalloc(&p->ws[2], (size_t)p->chunk * perc);
+            if (e == hipSuccess) e = hipMalloc(&p->ws3, std::max<size_t>(1, (size_t)p->chunk * per3));
+            if (e != hipSuccess) { amqft_plan_destroy(p); return hip_fail(e); }
+        }
+    } else if (mp && !(flags & AMQFT_FLAG_FORCE_MULTIPASS) &&
         (force_large ? kL_supported_forced(variant, logn, dtype) : kL_supported(variant, logn, dtype))) {
         // workspaces sized so that both stay within the last-level cache
         p->large = true;
@@ -575,6 +612,10 @@ amqft_status amqft_plan_create(amqft_plan* out, int64_t n, int64_t batch, amqft_
     if ((flags & AMQFT_FLAG_FORCE_LARGE) && !kL_supported_forced((int)variant, logn, (int)dtype))
         return AMQFT_ERR_UNSUPPORTED;
     const bool mp = logn > max_lds_log2((int)dtype) || (flags & kForceFlags);
+    if ((flags & AMQFT_FLAG_IN_PLACE) && mp &&
+        ((flags & AMQFT_FLAG_FORCE_MULTIPASS) ||
+         !kL_inplace_supported((int)variant, logn, (int)dtype, (flags & AMQFT_FLAG_FORCE_LARGE) != 0)))
+        return AMQFT_ERR_UNSUPPORTED;
     if (mp && logn < 5) return AMQFT_ERR_UNSUPPORTED;  // multi-pass needs a block of at least 8 points
     if (batch > (int64_t(1) << 40)) return AMQFT_ERR_UNSUPPORTED;
     return create_single(out, n, batch, (int)variant, (int)dtype, flags);
@@ -589,7 +630,7 @@ amqft_status amqft_plan_create_real(amqft_plan* out, int64_t n, int64_t batch, a
     if (flags & ~kAllFlags) return AMQFT_ERR_INVALID_ARG;
     const int logn = log2_exact(n);
     if (logn < 0) return AMQFT_ERR_NOT_POW2;
-    if (flags & (kForceFlags | AMQFT_FLAG_TRANSPOSED_ADJOINT)) return AMQFT_ERR_UNSUPPORTED;
+    if (flags & (kForceFlags | AMQFT_FLAG_TRANSPOSED_ADJOINT | AMQFT_FLAG_IN_PLACE)) return AMQFT_ERR_UNSUPPORTED;
     if (dtype != AMQFT_C128 && dtype != AMQFT_C64) return AMQFT_ERR_UNSUPPORTED;  // also no fixed point
     if (logn < 2 || logn > max_lds_log2((int)dtype)) return AMQFT_ERR_UNSUPPORTED;
     if (batch > (int64_t(1) << 40)) return AMQFT_ERR_UNSUPPORTED;
@@ -619,7 +660,7 @@ amqft_status amqft_plan_create_many(amqft_plan* out, int64_t count, const int64_
     if (!valid_variant((int)variant) || !valid_dtype((int)dtype) || count < 0) return AMQFT_ERR_INVALID_ARG;
     if (count > 0 && (!lengths_host || !offsets_host)) return AMQFT_ERR_INVALID_ARG;
     if (flags & ~kAllFlags) return AMQFT_ERR_INVALID_ARG;
-    if (flags & AMQFT_FLAG_TRANSPOSED_ADJOINT) return AMQFT_ERR_UNSUPPORTED;
+    if (flags & (AMQFT_FLAG_TRANSPOSED_ADJOINT | AMQFT_FLAG_IN_PLACE)) return AMQFT_ERR_UNSUPPORTED;
     if (dtype == AMQFT_C32I) return AMQFT_ERR_UNSUPPORTED;
     int maxlog = 2;
     for (int64_t i = 0; i < count; ++i) {
@@ -823,6 +864,8 @@ amqft_status amqft_plan_destroy(amqft_plan p) {
     if (p->ktab) (void)hipFree(p->ktab);
     for (void* w : p->ws)
         if (w) (void)hipFree(w);
+    if (p->ws3) (void)hipFree(p->ws3);
+    if (p->iptab) (void)hipFree(p->iptab);
     delete p;
     return AMQFT_OK;
 }
@@ -842,6 +885,9 @@ amqft_status amqft_plan_describe(amqft_plan p, char* buf, size_t len) {
         for (auto& c : p->classes) nclass += c.sub ? 1 : 0;
         snprintf(buf, len, "many-length plan: %lld signals, persistent kernel grid=%d items=%d, %d long-length classes",
                  (long long)p->count, p->grid, p->nitems, nclass);
+    } else if (p->inplace) {
+        snprintf(buf, len, "amqft_kL_{top_ip,rows,back_ip,bchain_ip}<%d> in place n=%lld chunk=%lld shared=%d",
+                 p->variant, (long long)p->n, (long long)p->chunk, p->ipnsh);
     } else if (p->large) {
         const bool transposed = p->variant == 2 || p->variant == 6;
         snprintf(buf, len, transposed       ? (p->logn >= 18 ? "amqft_kLT_{c0,fold,b0,rback,rows,rtop,top}<%d> n=%lld chunk=%lld"

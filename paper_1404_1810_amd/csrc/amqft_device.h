@@ -96,6 +96,20 @@ __device__ __forceinline__ cx<R> cconj(cx<R> a) { return {a.re, -a.im}; }
 
 // cos(pi/4) = sin(pi/4): the single constant of the L = 8 base cases of
 // dct_oo / dst_oo (Sec. 7.1).
+// Accesses of the in-place large-N path to the signal buffer, which it
+// rewrites in the positions it read (the CPU emulation of the kernels checks
+// that no workgroup touches a position that another workgroup of the same
+// launch writes).
+template <typename R>
+__device__ __forceinline__ cx<R> xld(const cx<R>* p) {
+    const cx<R> v = *p;  // in-place signal read
+    return v;
+}
+template <typename R>
+__device__ __forceinline__ void xst(cx<R>* p, cx<R> v) {
+    *p = v;  // in-place signal write
+}
+
 template <typename R> __device__ __forceinline__ R cos_pi_4();
 template <> __device__ __forceinline__ float cos_pi_4<float>() { return 0.70710678118654752440f; }
 template <> __device__ __forceinline__ double cos_pi_4<double>() { return 0.70710678118654752440; }

@@ -104,8 +104,17 @@ struct kl_launch {
     const void* ktab;  // table built for exactly N
     int conj_in, conj_out;
     const void* offsets = nullptr;
+    // in place (in == out; variants 4, 8, N = 2^11 .. 2^17, FP32 / FP64
+    // storage): ws1 unused, ws2 chunk * (N/8 + 16), ws3 chunk * 16 * ipnsh,
+    // iptab the slot table of amqft_iplayout.h on the device
+    int inplace = 0;
+    void* ws3 = nullptr;
+    const int* iptab = nullptr;
+    int ipnsh = 0;
 };
 bool kL_supported(int variant, int logn, int dtype);
+// sizes and types the in-place path takes
+bool kL_inplace_supported(int variant, int logn, int dtype, bool forced);
 // variants 2 and 6 on the transposed program of that path (amqft_kLT.hip):
 // N = 2^15 .. 2^17 (FP64 2^14 .. 2^16), forced from 2^11; kL_* below
 // dispatch to these for those variants

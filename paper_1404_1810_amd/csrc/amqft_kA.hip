@@ -284,6 +284,14 @@ struct global_layout {
     static constexpr int chain(int c) { return c; }
 };
 
+// member(r, o) of the in-place path: the position of row r's value in orbit o
+// (the orbit of a first-kernel thread: o + j N/8 and (j+1) N/8 - o)
+template <int LOGN>
+__device__ __forceinline__ int ip_member(int r, int o) {
+    constexpr int N8 = (1 << LOGN) / 8;
+    return r < 8 ? r * N8 + o : (r - 7) * N8 - o;
+}
+
 template <int V, typename S, int LOGN>
 __global__ __launch_bounds__(256) void amqft_kL_top(const S* __restrict__ in, cx<typename storage<S>::R>* __restrict__ ws1,
                                                      cx<typename storage<S>::R>* __restrict__ wsc,
@@ -311,14 +319,48 @@ __global__ __launch_bounds__(256) void amqft_kL_top(const S* __restrict__ in, cx
     }
 }
 
+// In place: thread m0 writes the sixteen row values of slot m0 to the sixteen
+// positions of orbit m0 it read (row r at ip_member(r, m0)); thread 0 reads
+// orbit 0 (the positions N/16 k) and writes the chain values to wsc.
+template <int V, typename S, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_top_ip(S* x, cx<typename storage<S>::R>* __restrict__ wsc,
+                                                        const typename storage<S>::R* __restrict__ ktab,
+                                                        long long sig0, long long batch, int flags) {
+    using R = typename storage<S>::R;
+    constexpr int N = 1 << LOGN, W3 = N / 16;
+    const int m0 = blockIdx.x * 256 + threadIdx.x;
+    const long long sl = blockIdx.y, gs = sig0 + sl;
+    if (gs >= batch || m0 >= W3) return;
+    const bool conj_in = flags & 1;
+    const long long base = uniform64(gs * (long long)N);
+    cx<R> raw[16];
+    f1_load<LOGN, S, R, true>(x + base, m0, raw);
+    cx<R>* sig = reinterpret_cast<cx<R>*>(x + base);
+    if (m0 > 0) {
+        cx<R> cd[2][8];
+        f1_dc<R>(raw, conj_in, cd);
+        f1_levels<V, LOGN, R>(ktab, cd, m0, [&](auto sc, auto pc, cx<R> v) {
+            constexpr int side = decltype(sc)::value, P8 = decltype(pc)::value;
+            xst(sig + ip_member<LOGN>(side * 8 + P8, m0), v);
+        });
+    } else {
+        f1_chain_to<V, LOGN, R>(ktab, raw, conj_in, [&](int c, cx<R> v) { wsc[sl * 16 + c] = v; });
+    }
+}
+
 // Rows at depth DEP (3, or 6 for N >= 2^18): a pair of rows of the two
 // contexts is the pair of sides of a 2^(log2 N - DEP)-point transform.  Depth-3
 // rows live in ws by side (row (side, P) at (8 side + P) W), depth-6 rows by
 // context (row (P, h) at (2 P + h) W); either way the pair leaves in the
 // block layout of the row (block a at W - W / 2^a).
-template <int V, typename R, int LOGN, int DEP>
+//
+// IP (in place, depth 3): ws1 is the signal buffer; slot s of row r is read
+// at ip_member(r, s) and written at ip_member(r, orb[s]).  The workgroup
+// reads all of its rows before its first barrier.
+template <int V, typename R, int LOGN, int DEP, bool IP = false>
 __global__ __launch_bounds__(kgeo<LOGN - DEP>::WG) void amqft_kL_rows(cx<R>* __restrict__ ws1,
-                                                                      const R* __restrict__ ktab) {
+                                                                      const R* __restrict__ ktab,
+                                                                      const int* __restrict__ orb) {
     constexpr int LR = LOGN - DEP;  // rows = sides of a 2^LR-point transform
     using G = kgeo<LR>;
     constexpr bool SW = variant_traits<V>::switches;
@@ -337,24 +379,37 @@ __global__ __launch_bounds__(kgeo<LOGN - DEP>::WG) void amqft_kL_rows(cx<R>* __r
     cx<R>* sig = ws1 + (long long)blockIdx.y * (1 << LOGN);
     // half hh (= context) holds the row of side hh ^ parity(P) (depth 3) or
     // the row of context hh (depth 6)
+    static_assert(!IP || DEP == 3, "the in-place layout is that of depth-3 rows");
     cx<R>* row[2];
+    int rid[2];
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh)
-        row[hh] = DEP == 3 ? sig + ((hh ^ (SW ? par(P) : 0)) * 8 + P) * W3 : sig + (2 * P + hh) * W3;
+    for (int hh = 0; hh < 2; ++hh) {
+        rid[hh] = (hh ^ (SW ? par(P) : 0)) * 8 + P;
+        row[hh] = DEP == 3 ? sig + rid[hh] * W3 : sig + (2 * P + hh) * W3;
+    }
+    // slot q of the row in half hh: the input layout, and the output layout
+    auto rd = [&](int hh, int q) {
+        if constexpr (IP) return xld(sig + ip_member<LOGN>(rid[hh], q));
+        else return row[hh][q];
+    };
+    auto wr = [&](int hh, int q, cx<R> v) {
+        if constexpr (IP) xst(sig + ip_member<LOGN>(rid[hh], orb[q]), v);
+        else row[hh][q] = v;
+    };
     cx<R> cd[2][8];
     if (m0 > 0) {
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                cd[hh][2 * i] = row[hh][m0 + N8r * i];
-                cd[hh][2 * i + 1] = row[hh][N8r * (i + 1) - m0];
+                cd[hh][2 * i] = rd(hh, m0 + N8r * i);
+                cd[hh][2 * i + 1] = rd(hh, N8r * (i + 1) - m0);
             }
     } else {
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
-            for (int k = 1; k < 8; ++k) cd[hh][k] = row[hh][(W3 / 8) * k];
+            for (int k = 1; k < 8; ++k) cd[hh][k] = rd(hh, (W3 / 8) * k);
     }
     fill_constants<V, LR, R>(kt, kf, ktab, DEP, false, tid);
     __syncthreads();
@@ -373,10 +428,10 @@ __global__ __launch_bounds__(kgeo<LOGN - DEP>::WG) void amqft_kL_rows(cx<R>* __r
             leaf::ot<V, 4, hh, R>(b4, kt, G::D);
             leaf::ot<V, 2, hh, R>(b2, kt, G::D);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) row[hh][W3 - 8 + i] = b4[i];
-            row[hh][W3 - 4] = b2[0];
-            row[hh][W3 - 3] = b2[1];
-            row[hh][W3 - 2] = cd[hh][4];
+            for (int i = 0; i < 4; ++i) wr(hh, W3 - 8 + i, b4[i]);
+            wr(hh, W3 - 4, b2[0]);
+            wr(hh, W3 - 3, b2[1]);
+            wr(hh, W3 - 2, cd[hh][4]);
         });
     }
     __syncthreads();
@@ -387,7 +442,7 @@ __global__ __launch_bounds__(kgeo<LOGN - DEP>::WG) void amqft_kL_rows(cx<R>* __r
     // blocks with at least 8 points: LDS block layout -> the row
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh)
-        for (int pos = m0; pos < W3 - 8; pos += G::T) row[hh][pos] = ldc(w + hh * G::HS + pad(pos));
+        for (int pos = m0; pos < W3 - 8; pos += G::T) wr(hh, pos, ldc(w + hh * G::HS + pad(pos)));
 }
 
 // N >= 2^18: levels 3..5 of every depth-3 row pair (the F1 levels of its
@@ -484,8 +539,14 @@ __global__ __launch_bounds__(256) void amqft_kL_rback(const cx<R>* __restrict__ 
 // B0 of one position p of the depth-3 block layout (block a, index j): the
 // eight rows of each side at p - 1, p, p + 1 (neighbours outside the block
 // count as zero) give harmonics 8j .. 8j + 7 of depth-0 block a of both sides.
-template <int V, typename R, int LOGN>
-__device__ __forceinline__ void b0_group(const cx<R>* __restrict__ sig, int p, cx<R> (&o)[2][8]) {
+// B0 (levels 2..0) of the group of depth-3 slot p of the sixteen rows: the
+// eight harmonics per side it expands to.  ld(r, s) reads slot s of row
+// (side, q) = r / 8, r % 8.  COND: read the neighbour slots only where the
+// group has neighbours in its block (the in-place path, whose slots past a
+// block's ends may belong to another workgroup); otherwise read them always
+// and discard.
+template <int V, typename R, int LOGN, bool COND = false, typename LD>
+__device__ __forceinline__ void b0_group(LD&& ld, int p, cx<R> (&o)[2][8]) {
     constexpr int N = 1 << LOGN, W3 = N / 16, LW3 = ilog2c(W3);
     const int a = __clz(~(p << (32 - LW3)));  // block of position p in the row's block layout
     const int j = p - (W3 - (W3 >> a));
@@ -496,11 +557,17 @@ __device__ __forceinline__ void b0_group(const cx<R>* __restrict__ sig, int p, c
     for (int side = 0; side < 2; ++side)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const cx<R>* row = sig + (side * 8 + q) * W3;
-            const cx<R> lm = row[pm], lp = row[p + 1];
-            ext[side][q][0] = j >= 1 ? lm : zero<R>();
-            ext[side][q][1] = row[p];
-            ext[side][q][2] = j + 1 < sp ? lp : zero<R>();
+            const int r = side * 8 + q;
+            if constexpr (COND) {
+                ext[side][q][0] = j >= 1 ? ld(r, p - 1) : zero<R>();
+                ext[side][q][1] = ld(r, p);
+                ext[side][q][2] = j + 1 < sp ? ld(r, p + 1) : zero<R>();
+            } else {
+                const cx<R> lm = ld(r, pm), lp = ld(r, p + 1);
+                ext[side][q][0] = j >= 1 ? lm : zero<R>();
+                ext[side][q][1] = ld(r, p);
+                ext[side][q][2] = j + 1 < sp ? lp : zero<R>();
+            }
         }
     bwd_run<V, 0, 3, R>(ext[0], o[0]);
     bwd_run<V, 1, 3, R>(ext[1], o[1]);
@@ -530,12 +597,63 @@ __global__ __launch_bounds__(64) void amqft_kL_back(const cx<R>* __restrict__ ws
     const int a = __clz(~(p << (32 - LW3)));
     const int j = p - (W3 - (W3 >> a));
     cx<R> o[2][8];
-    b0_group<V, R, LOGN>(ws1 + (long long)blockIdx.y * N, p, o);
+    const cx<R>* sig = ws1 + (long long)blockIdx.y * N;
+    b0_group<V, R, LOGN>([&](int r, int q) { return sig[r * W3 + q]; }, p, o);
     cx<R>* out = ws2 + (long long)blockIdx.y * N + (H - (H >> a)) + 8 * j;
 #pragma unroll
     for (int e = 0; e < 8; ++e) out[e] = o[0][e];
 #pragma unroll
     for (int e = 0; e < 8; ++e) out[H + e] = o[1][e];
+}
+
+// In place: the same groups read from the signal buffer x (slot s of row r at
+// ip_member(r, orb[s])); blocks >= 3 -> ws2 at side H/8 + (block a of side 0
+// at H/8 - H/2^a), the fourteen groups -> the one value of each that thread
+// k0 = 0 reads (DCT side at element 0 of the even groups, DST side at element
+// 7 of the odd ones) at ws2 + N/8; and the slots that two workgroups of the
+// chain kernel read, 16 rows each, -> ws3.
+template <int V, typename R, int LOGN>
+__global__ __launch_bounds__(64) void amqft_kL_back_ip(const cx<R>* x, cx<R>* __restrict__ ws2,
+                                                        cx<R>* __restrict__ ws3, const int* __restrict__ iptab,
+                                                        int nsh, long long sig0) {
+    constexpr int N = 1 << LOGN, H = N / 2, W3 = N / 16, NB3 = W3 / 8 - 1, GA = N / 128;
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= NB3 + 14 + nsh) return;
+    const long long sl = blockIdx.y;
+    const cx<R>* sig = x + (sig0 + sl) * N;
+    const int* orb = iptab;
+    auto ld = [&](int r, int q) { return xld(sig + ip_member<LOGN>(r, orb[q])); };
+    cx<R>* w2 = ws2 + sl * (N / 8 + 16);
+    if (i >= NB3 + 14) {
+        const int k = i - NB3 - 14, q = iptab[2 * W3 + k];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ws3[(sl * nsh + k) * 16 + r] = ld(r, q);
+        return;
+    }
+    int p, y = 0;
+    if (i < NB3) {
+        p = W3 - W3 / 8 + i;
+    } else {
+        const int xg = i - NB3;
+        const int a = xg < 8 ? 0 : xg < 12 ? 1 : 2;
+        y = xg - (xg < 8 ? 0 : xg < 12 ? 8 : 12);
+        const int g = ((y + 1) >> 1) * GA - (y & 1);
+        p = W3 - (W3 >> a) + g;
+    }
+    cx<R> o[2][8];
+    b0_group<V, R, LOGN, true>(ld, p, o);
+    if (i < NB3) {
+        constexpr int LW3 = ilog2c(W3);
+        const int a = __clz(~(p << (32 - LW3)));
+        const int j = p - (W3 - (W3 >> a));
+        cx<R>* out = w2 + (H / 8 - (H >> a)) + 8 * j;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) out[e] = o[0][e];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) out[H / 8 + e] = o[1][e];
+    } else {
+        w2[N / 8 + i - NB3] = (y & 1) ? o[1][7] : o[0][0];
+    }
 }
 
 // B0 for blocks 0..2 and the chain in one kernel.  Workgroup K/256 serves
@@ -548,15 +666,23 @@ __global__ __launch_bounds__(64) void amqft_kL_back(const cx<R>* __restrict__ ws
 template <typename R>
 constexpr size_t kL_bchain_lds() { return 2 * 7 * 34 * 8 * sizeof(cx<R>); }
 
-template <int V, typename S, int LOGN>
-__global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage<S>::R>* __restrict__ ws1,
-                                                        const cx<typename storage<S>::R>* __restrict__ ws2,
-                                                        const cx<typename storage<S>::R>* __restrict__ wsc,
-                                                        S* __restrict__ out, long long sig0, long long batch, int flags,
-                                                        const long long* __restrict__ offsets) {
+// The kernel body; IP: the in-place path, where ws1 is the signal buffer
+// itself (rows at member(r, orb[s]), the slots two workgroups read taken from
+// ws3), ws2 holds only the blocks >= 3 of each side (H/8 values a side) and
+// then the fourteen values thread k0 = 0 reads from blocks 0..2.
+template <int V, typename S, int LOGN, bool IP>
+__device__ __forceinline__ void kL_bchain_body(const cx<typename storage<S>::R>* ws1,
+                                               const cx<typename storage<S>::R>* ws2,
+                                               const cx<typename storage<S>::R>* ws3,
+                                               const cx<typename storage<S>::R>* wsc, S* out, const int* iptab,
+                                               int nsh, long long sig0, long long batch, int flags,
+                                               const long long* offsets) {
     using R = typename storage<S>::R;
     constexpr int N = 1 << LOGN, H = N / 2, Q = N / 4, W3 = N / 16, N8 = N / 8, D = LOGN - 2;
     constexpr int NG = 34, NWIN = 7, WS = NG * 8, NW = D - 5;
+    // ws2 per signal and the offset of block a of side s in it
+    constexpr long long W2 = IP ? N / 8 + 16 : N;
+    constexpr int GOFF = IP ? H - H / 8 : 0, SIDE2 = IP ? H / 8 : H;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<R>(*blk)[NWIN * WS] = reinterpret_cast<cx<R>(*)[NWIN * WS]>(smem);  // [side][slot]
     // Every workgroup of a signal reads the signal's blocks >= 3 (ws2) at
@@ -583,7 +709,20 @@ __global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage
         const int g = wg0(r) + (tid - r * NG);
         if (g >= 0 && g < (W3 >> (a + 1))) {
             cx<R> o[2][8];
-            b0_group<V, R, LOGN>(ws1 + sl * N, W3 - (W3 >> a) + g, o);
+            if constexpr (IP) {
+                const long long gsb = gs * (long long)N;
+                const int* orb = iptab;
+                const int* shx = iptab + W3;
+                b0_group<V, R, LOGN, true>(
+                    [&](int r, int q) {
+                        const int x = shx[q];
+                        return x >= 0 ? ws3[(sl * nsh + x) * 16 + r] : xld(ws1 + gsb + ip_member<LOGN>(r, orb[q]));
+                    },
+                    W3 - (W3 >> a) + g, o);
+            } else {
+                const cx<R>* sig = ws1 + sl * N;
+                b0_group<V, R, LOGN>([&](int r, int q) { return sig[r * W3 + q]; }, W3 - (W3 >> a) + g, o);
+            }
 #pragma unroll
             for (int side = 0; side < 2; ++side)
 #pragma unroll
@@ -593,15 +732,28 @@ __global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage
     __syncthreads();
     const int k0 = K + tid;
     if (k0 >= W3) return;  // N < 2^12: fewer chain threads than the workgroup has
-    const cx<R>* w2 = ws2 + sl * N;
+    const cx<R>* w2 = ws2 + sl * W2;
     const cx<R>* chn = wsc + sl * 16;
     cx<R> res[16];
     if (k0 == 0) {
-        c0_compute<LOGN, R, global_layout<LOGN>>(w2, chn, 0, res);
+        if constexpr (IP) {
+            // blocks >= 3 at harmonic 0; blocks 0..2 at the harmonics N/16 i
+            // (DCT side) and N/16 i - 1 (DST side), in the order the back
+            // kernel stores them: block 0 i = 0..3 / 1..4, block 1 i = 0, 1 /
+            // 1, 2, block 2 i = 0 / 1
+            constexpr int N16 = N / 16;
+            const cx<R>* z = w2 + N / 8;
+            auto zb = [](int a) { return a == 0 ? 0 : a == 1 ? 8 : 12; };
+            c0_zero<LOGN, R>(
+                [&](int a, int k) { return a >= 3 ? w2[H / 8 - (H >> a) + k] : z[zb(a) + 2 * (k / N16)]; },
+                [&](int a, int k) { return z[zb(a) + 2 * (k / N16) - 1]; }, chn[0], res);
+        } else {
+            c0_compute<LOGN, R, global_layout<LOGN>>(w2, chn, 0, res);
+        }
     } else {
         // harmonic k of window r, side s
         auto lw = [&](int s, int r, int k) { return ldc(&blk[s][r * WS + k - 8 * wg0(r)]); };
-        auto gb = [](int a) { return H - (H >> a); };  // block a of side 0 in ws2
+        auto gb = [](int a) { return H - (H >> a) - GOFF; };  // block a of side 0 in ws2
         auto lo = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re + Dv.im, Cv.im - Dv.re}; };
         auto hi = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re - Dv.im, Cv.im + Dv.re}; };
         // the chain walk: folded indices and signs, as in the LDS kernel's C0
@@ -638,7 +790,7 @@ __global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage
         cx<R> accs = ldc(chn + 8 + e8) * wd;
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
-            const cx<R> o = ldc(w2 + H + gb(3 + t) + is[t] - 1);
+            const cx<R> o = ldc(w2 + SIDE2 + gb(3 + t) + is[t] - 1);
             accs = cx<R>{accs.re + wsg[t] * o.re, accs.im + wsg[t] * o.im};
         }
         cx<R> accc = ldc(chn + kc);
@@ -692,7 +844,66 @@ __global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage
 }
 
 template <int V, typename S, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_bchain(const cx<typename storage<S>::R>* __restrict__ ws1,
+                                                        const cx<typename storage<S>::R>* __restrict__ ws2,
+                                                        const cx<typename storage<S>::R>* __restrict__ wsc,
+                                                        S* __restrict__ out, long long sig0, long long batch, int flags,
+                                                        const long long* __restrict__ offsets) {
+    kL_bchain_body<V, S, LOGN, false>(ws1, ws2, nullptr, wsc, out, nullptr, 0, sig0, batch, flags, offsets);
+}
+
+// in place: x is read (rows) and written (the transform) by the same
+// workgroup only, its reads before a barrier and its writes after
+template <int V, typename S, int LOGN>
+__global__ __launch_bounds__(256) void amqft_kL_bchain_ip(S* x, const cx<typename storage<S>::R>* __restrict__ ws2,
+                                                           const cx<typename storage<S>::R>* __restrict__ ws3,
+                                                           const cx<typename storage<S>::R>* __restrict__ wsc,
+                                                           const int* __restrict__ iptab, int nsh, long long sig0,
+                                                           long long batch, int flags) {
+    using R = typename storage<S>::R;
+    kL_bchain_body<V, S, LOGN, true>(reinterpret_cast<const cx<R>*>(x), ws2, ws3, wsc, x, iptab, nsh, sig0, batch,
+                                     flags, nullptr);
+}
+
+// The in-place path (N/16 rows of depth 3; FP32 and FP64 storage): the
+// signal buffer a.out (= a.in) holds the rows between the kernels; ws2 holds
+// N/8 + 16 values a signal, ws3 16 per shared slot, wsc 16.
+template <int V, typename S, int LOGN>
+hipError_t launch_kL_ip_n(const kl_launch& a, hipStream_t st) {
+    using R = typename storage<S>::R;
+    constexpr int N = 1 << LOGN, W3 = N / 16, NB3 = W3 / 8 - 1;
+    using GR = kgeo<LOGN - 3>;
+    const int flags = (a.conj_in ? 1 : 0) | (a.conj_out ? 2 : 0);
+    const size_t lds = kA_lds_bytes<R, LOGN - 3>();
+    S* x = static_cast<S*>(a.out);
+    cx<R>* ws2 = static_cast<cx<R>*>(a.ws2);
+    cx<R>* ws3 = static_cast<cx<R>*>(a.ws3);
+    cx<R>* wsc = static_cast<cx<R>*>(a.wsc);
+    const R* kt = static_cast<const R*>(a.ktab);
+    for (long long s0 = 0; s0 < a.batch; s0 += a.chunk) {
+        const long long nb = a.batch - s0 < a.chunk ? a.batch - s0 : a.chunk;
+        const dim3 gw((W3 + 255) / 256, (unsigned)nb);
+        hipLaunchKernelGGL((amqft_kL_top_ip<V, S, LOGN>), gw, dim3(256), 0, st, x, wsc, kt, s0, (long long)a.batch,
+                           flags);
+        hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN, 3, true>), dim3(8 / GR::SPW, (unsigned)nb), dim3(GR::WG), lds, st,
+                           reinterpret_cast<cx<R>*>(x + s0 * N), kt, a.iptab);
+        hipLaunchKernelGGL((amqft_kL_back_ip<V, R, LOGN>), dim3((NB3 + 14 + a.ipnsh + 63) / 64, (unsigned)nb), dim3(64),
+                           0, st, reinterpret_cast<const cx<R>*>(x), ws2, ws3, a.iptab, a.ipnsh, s0);
+        hipLaunchKernelGGL((amqft_kL_bchain_ip<V, S, LOGN>), gw, dim3(256), kL_bchain_lds<R>(), st, x,
+                           static_cast<const cx<R>*>(ws2), static_cast<const cx<R>*>(ws3),
+                           static_cast<const cx<R>*>(wsc), a.iptab, a.ipnsh, s0, (long long)a.batch, flags);
+    }
+    return hipGetLastError();
+}
+
+template <int V, typename S, int LOGN>
 hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
+    constexpr int DEP_ = (1 << LOGN) >= (1 << 18) ? 6 : 3;
+    if constexpr (DEP_ == 3 && (std::is_same<S, float2>::value || std::is_same<S, double2>::value)) {
+        if (a.inplace) return launch_kL_ip_n<V, S, LOGN>(a, st);
+    } else {
+        if (a.inplace) return hipErrorInvalidValue;
+    }
     using R = typename storage<S>::R;
     constexpr int N = 1 << LOGN, W3 = N / 16;
     constexpr int DEP = LOGN >= 18 ? 6 : 3;  // depth of the rows that fit one workgroup's LDS
@@ -710,13 +921,14 @@ hipError_t launch_kL_n(const kl_launch& a, hipStream_t st) {
                            s0, (long long)a.batch, flags, static_cast<const long long*>(a.offsets));
         if constexpr (DEP == 3) {
             hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN, 3>), dim3(8 / GR::SPW, (unsigned)nb), dim3(GR::WG), lds, st, ws1,
-                               kt);
+                               kt, nullptr);
         } else {
             constexpr int W6 = N / 128;
             hipLaunchKernelGGL((amqft_kL_rtop<V, R, LOGN>), dim3(W6 / 256, 8, (unsigned)nb), dim3(256), 0, st, ws1, ws2,
                                kt);
             static_assert(GR::SPW == 1, "depth-6 rows are at least 2^12 points");
-            hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN, 6>), dim3(64, (unsigned)nb), dim3(GR::WG), lds, st, ws2, kt);
+            hipLaunchKernelGGL((amqft_kL_rows<V, R, LOGN, 6>), dim3(64, (unsigned)nb), dim3(GR::WG), lds, st, ws2, kt,
+                               nullptr);
             hipLaunchKernelGGL((amqft_kL_rback<V, R, LOGN>), dim3(W6 / 256, 16, (unsigned)nb), dim3(256), 0, st,
                                static_cast<const cx<R>*>(ws2), ws1);
         }
@@ -770,6 +982,11 @@ hipError_t prime_kL_n() {
     constexpr int DEP = LOGN >= 18 ? 6 : 3;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kL_rows<V, R, LOGN, DEP>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if constexpr (DEP == 3) {
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&amqft_kL_rows<V, R, LOGN, 3, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    }
     if constexpr (LOGN < LMAX) {
         if (e == hipSuccess) e = prime_kL_n<V, R, LOGN + 1, LMAX>();
     }
@@ -877,6 +1094,13 @@ bool kL_supported_forced(int variant, int logn, int dtype) {
     return kL_supported(variant, logn, dtype);
 }
 
+bool kL_inplace_supported(int variant, int logn, int dtype, bool forced) {
+    if (variant != 4 && variant != 8) return false;
+    if (dtype == 0) return logn >= (forced ? 11 : 14) && logn <= 16;
+    if (dtype == 1) return logn >= (forced ? 11 : 15) && logn <= 17;
+    return false;  // FP16 / BF16 storage would round the rows kept in the buffer
+}
+
 size_t kL_ws_bytes_per_signal(int logn, int dtype) { return ((size_t)1 << logn) * (dtype == 0 ? 16 : 8); }
 
 hipError_t prime_kL(int variant, int dtype) {
@@ -899,6 +1123,8 @@ static hipError_t launch_kL_t(const kl_launch& a, hipStream_t st) {
 
 hipError_t launch_kL(const kl_launch& a, hipStream_t st) {
     if (a.batch <= 0) return hipSuccess;
+    if (a.inplace && (a.in != a.out || !kL_inplace_supported(a.variant, a.logn, a.dtype, true)))
+        return hipErrorInvalidValue;
     if (a.variant == 2 || a.variant == 6) return launch_kLT(a, st);
     if (a.variant == 4) return launch_kL_t<4>(a, st);
     return launch_kL_t<8>(a, st);

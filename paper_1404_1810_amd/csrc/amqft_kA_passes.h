@@ -1111,6 +1111,57 @@ struct lds_layout {
     static constexpr int chain(int c) { return (c >> 3) * G::HS + (c & 7) * G::W3P + 16; }
 };
 
+// C0 of the chain thread k0 = 0 (harmonics N/16 i): Oc(a, k) / Os(a, k) read
+// harmonic k of block a on the DCT / DST side (the DST side stores harmonic k
+// at k - 1); e8_0 is chain value 0
+template <int LOGN, typename R, typename OC, typename OS>
+__device__ __forceinline__ void c0_zero(OC&& Oc, OS&& Os, cx<R> e8_0, cx<R> (&res)[16]) {
+    using G = kgeo<LOGN>;
+    constexpr int D = G::D, N16 = G::N / 16;
+    auto lo = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re + Dv.im, Cv.im - Dv.re}; };
+    auto hi = [](cx<R> Cv, cx<R> Dv) { return cx<R>{Cv.re - Dv.im, Cv.im + Dv.re}; };
+    // harmonics N16 i: E_3(0) and E_3(N16) (the top harmonic of periodization 32 q_3)
+    cx<R> sum47 = zero<R>();
+#pragma unroll
+    for (int a = 4; a <= D - 3; ++a) sum47 = sum47 + Oc(a, 0);
+    const cx<R> o3 = Oc(3, 0);
+    const cx<R> E3_0 = e8_0 + sum47 + o3;
+    const cx<R> E3_h = e8_0 + sum47 - o3;
+    const cx<R> o2 = Oc(2, 0);
+    const cx<R> E2_0 = E3_0 + o2, E2_2 = E3_0 - o2, E2_1 = E3_h;
+    const cx<R> o1_0 = Oc(1, 0), o1_1 = Oc(1, N16);
+    const cx<R> E1_0 = E2_0 + o1_0, E1_4 = E2_0 - o1_0;
+    const cx<R> E1_1 = E2_1 + o1_1, E1_3 = E2_1 - o1_1, E1_2 = E2_2;
+    cx<R> C[9];
+    const cx<R> E1v[4] = {E1_0, E1_1, E1_2, E1_3};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const cx<R> o0 = Oc(0, N16 * i);
+        C[i] = E1v[i] + o0;
+        C[8 - i] = E1v[i] - o0;
+    }
+    C[4] = E1_4;
+    const cx<R> D2_1 = Os(2, N16);
+    const cx<R> p1 = Os(1, N16);
+    const cx<R> D1v[4] = {zero<R>(), p1 + D2_1, Os(1, 2 * N16), p1 - D2_1};
+    cx<R> Dd[9];
+    Dd[0] = zero<R>();
+    Dd[8] = zero<R>();
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+        const cx<R> o0 = Os(0, N16 * i);
+        Dd[i] = o0 + D1v[i];
+        Dd[8 - i] = o0 - D1v[i];
+    }
+    Dd[4] = Os(0, 4 * N16);
+    res[0] = C[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) res[i] = lo(C[i], Dd[i]);
+    res[8] = C[8];
+#pragma unroll
+    for (int i = 9; i < 16; ++i) res[i] = hi(C[16 - i], Dd[16 - i]);
+}
+
 template <int LOGN, typename R, typename L>
 __device__ __forceinline__ void c0_compute(const cx<R>* w, const cx<R>* chn, int k0, cx<R> (&res)[16]) {
     using G = kgeo<LOGN>;
@@ -1214,47 +1265,7 @@ __device__ __forceinline__ void c0_compute(const cx<R>* w, const cx<R>* chn, int
     } else {
         auto Oc = [&](int a, int k) { return ldc(w + bo(a) + L::idx(k)); };
         auto Os = [&](int a, int k) { return ldc(w + HSL + bo(a) + L::idx(k - 1)); };
-        // harmonics N16 i: E_3(0) and E_3(N16) (the top harmonic of periodization 32 q_3)
-        cx<R> sum47 = zero<R>();
-#pragma unroll
-        for (int a = 4; a <= D - 3; ++a) sum47 = sum47 + Oc(a, 0);
-        const cx<R> e8_0 = ldc(chn + L::chain(0));
-        const cx<R> o3 = Oc(3, 0);
-        const cx<R> E3_0 = e8_0 + sum47 + o3;
-        const cx<R> E3_h = e8_0 + sum47 - o3;
-        const cx<R> o2 = Oc(2, 0);
-        const cx<R> E2_0 = E3_0 + o2, E2_2 = E3_0 - o2, E2_1 = E3_h;
-        const cx<R> o1_0 = Oc(1, 0), o1_1 = Oc(1, N16);
-        const cx<R> E1_0 = E2_0 + o1_0, E1_4 = E2_0 - o1_0;
-        const cx<R> E1_1 = E2_1 + o1_1, E1_3 = E2_1 - o1_1, E1_2 = E2_2;
-        cx<R> C[9];
-        const cx<R> E1v[4] = {E1_0, E1_1, E1_2, E1_3};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const cx<R> o0 = Oc(0, N16 * i);
-            C[i] = E1v[i] + o0;
-            C[8 - i] = E1v[i] - o0;
-        }
-        C[4] = E1_4;
-        const cx<R> D2_1 = Os(2, N16);
-        const cx<R> p1 = Os(1, N16);
-        const cx<R> D1v[4] = {zero<R>(), p1 + D2_1, Os(1, 2 * N16), p1 - D2_1};
-        cx<R> Dd[9];
-        Dd[0] = zero<R>();
-        Dd[8] = zero<R>();
-#pragma unroll
-        for (int i = 1; i < 4; ++i) {
-            const cx<R> o0 = Os(0, N16 * i);
-            Dd[i] = o0 + D1v[i];
-            Dd[8 - i] = o0 - D1v[i];
-        }
-        Dd[4] = Os(0, 4 * N16);
-        res[0] = C[0];
-#pragma unroll
-        for (int i = 1; i < 8; ++i) res[i] = lo(C[i], Dd[i]);
-        res[8] = C[8];
-#pragma unroll
-        for (int i = 9; i < 16; ++i) res[i] = hi(C[16 - i], Dd[16 - i]);
+        c0_zero<LOGN, R>(Oc, Os, ldc(chn + L::chain(0)), res);
     }
 }
 

@@ -5,7 +5,8 @@ tests/emu/shim under AddressSanitizer and UndefinedBehaviorSanitizer.  Two
 textual changes are made to copies of the sources: the dynamic-LDS
 declaration becomes a pointer to the emulated workgroup's LDS block, and the
 whole-value LDS accessors ldc / stc of amqft_device.h report every access to
-the shim's barrier-interval race checker.  Objects are cached under
+the shim's barrier-interval race checker, and the in-place path's signal
+accessors xld / xst report to its cross-workgroup checker.  Objects are cached under
 _build/emu by a hash of their inputs."""
 from __future__ import annotations
 
@@ -20,7 +21,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1404_1810_amd", "csrc")
 OUT_DIR = os.path.join(ROOT, "_build", "emu")
 KERNELS = ["amqft_kA.hip", "amqft_lds.hip", "amqft_fast.hip", "amqft_kB.hip", "amqft_kLT.hip"]
-HEADERS = ["amqft_device.h", "amqft_internal.h", "amqft_levels.h", "amqft_leaf.h", "amqft_kA_passes.h", "amqft_kB_passes.h"]
+HEADERS = ["amqft_device.h", "amqft_internal.h", "amqft_levels.h", "amqft_leaf.h", "amqft_kA_passes.h", "amqft_kB_passes.h",
+           "amqft_iplayout.h"]
 CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 SMEM = re.compile(r"extern\s+__shared__\s+__align__\(\d+\)\s+unsigned\s+char\s+smem\[\];")
 FLAGS = ["-std=c++20", "-O0", "-gline-tables-only", "-ffp-contract=off", "-fno-omit-frame-pointer",
@@ -41,6 +43,12 @@ def _transform_header(name: str, text: str) -> str:
         assert a in text and b in text, "fixed-point ldc / stc bodies changed: update the emulation transform"
         text = text.replace(a, "    ::emu::lds_touch(p, sizeof(cx<fx32>), false);\n" + a)
         text = text.replace(b, "    ::emu::lds_touch(p, sizeof(cx<fx32>), true);\n" + b)
+        # the in-place path's signal accesses
+        a = "    const cx<R> v = *p;  // in-place signal read"
+        b = "    *p = v;  // in-place signal write"
+        assert a in text and b in text, "xld / xst bodies changed: update the emulation transform"
+        text = text.replace(a, "    ::emu::global_touch(p, sizeof(cx<R>), false);\n" + a)
+        text = text.replace(b, "    ::emu::global_touch(p, sizeof(cx<R>), true);\n" + b)
     return text
 
 

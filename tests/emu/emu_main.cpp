@@ -2,8 +2,13 @@
 //   amqft_emu PATH VARIANT DTYPE LOGN BATCH CONJ IN OUT
 // PATH: lds (the dispatch of launch_lds: compile-time kernels where they
 // exist), generic (the level engine), large (the top/rows/back/bchain
-// kernels of variants 4 and 8 over malloc'd workspaces), tkernel (the
-// transposed compile-time kernel).  DTYPE 0 = complex FP64, 1 = complex FP32,
+// kernels of variants 4 and 8 over malloc'd workspaces), large_ip (the
+// in-place form of that path: the input is copied to the output buffer, which
+// the path then transforms in place; with EMU_TRACK_GLOBAL=1 the shim checks
+// that no workgroup touches a word another workgroup of the same launch
+// writes), large_ip_naive (the same with a slot layout that ignores which
+// workgroup reads a slot: the checker's own test), tkernel (the transposed
+// compile-time kernel).  DTYPE 0 = complex FP64, 1 = complex FP32,
 // 4 = complex int32 fixed point (Q2.29 constants).
 // IN / OUT: raw interleaved complex arrays of BATCH x 2^LOGN values.
 // The constant table is built on the host in long double and rounded once.
@@ -16,6 +21,7 @@
 
 #include "amqft_device.h"
 #include "amqft_internal.h"
+#include "amqft_iplayout.h"
 
 using namespace amqft;
 
@@ -88,12 +94,50 @@ int main(int argc, char** argv) {
         k.conj_in = conj;
         k.conj_out = conj;
         e = launch_kL(k, nullptr);
+    } else if (path == "large_ip" || path == "large_ip_naive") {
+        kl_launch k{};
+        k.variant = variant;
+        k.dtype = dtype;
+        k.logn = logn;
+        k.batch = batch;
+        k.chunk = batch > 1 ? batch - 1 : 1;  // two chunks when the batch allows
+        std::vector<int> tab;
+        int nsh = ip_layout_build(logn, tab);
+        if (nsh < 0) { std::fprintf(stderr, "no in-place layout\n"); return 2; }
+        if (path == "large_ip_naive") {
+            // a layout that ignores which chain workgroup reads a slot (slot s
+            // in orbit s + 1, nothing shared): the checker must object
+            const int w3 = (int)(n / 16);
+            for (int q = 0; q < w3 - 1; ++q) tab[q] = q + 1;
+            for (int q = 0; q < w3; ++q) tab[w3 + q] = -1;
+            tab.resize(2 * w3);
+            nsh = 0;
+        }
+        std::vector<unsigned char> ws2((size_t)k.chunk * (n / 8 + 16) * esz),
+            ws3((size_t)k.chunk * (nsh > 0 ? nsh : 1) * 16 * esz), wsc((size_t)k.chunk * 16 * esz);
+        std::memcpy(out.data(), in.data(), in.size());
+        k.in = out.data();
+        k.out = out.data();
+        k.ws2 = ws2.data();
+        k.ws3 = ws3.data();
+        k.wsc = wsc.data();
+        k.iptab = tab.data();
+        k.ipnsh = nsh;
+        k.inplace = 1;
+        k.ktab = kt.data();
+        k.conj_in = conj;
+        k.conj_out = conj;
+        e = launch_kL(k, nullptr);
     } else {
         std::fprintf(stderr, "unknown path %s\n", path.c_str());
         return 2;
     }
     if (e != hipSuccess) { std::fprintf(stderr, "launch failed %d\n", (int)e); return 3; }
     if (emu::g_races.load() > 0) { std::fprintf(stderr, "%ld LDS races\n", emu::g_races.load()); return 4; }
+    if (emu::g_global_races.load() > 0) {
+        std::fprintf(stderr, "%ld cross-workgroup hazards\n", emu::g_global_races.load());
+        return 5;
+    }
     f = std::fopen(argv[8], "wb");
     if (!f || std::fwrite(out.data(), 1, out.size(), f) != out.size()) { std::fprintf(stderr, "bad output\n"); return 2; }
     std::fclose(f);

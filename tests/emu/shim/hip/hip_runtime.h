@@ -18,6 +18,7 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #define __global__
@@ -83,6 +84,43 @@ inline thread_local dim3 t_blockDim{1, 1, 1}, t_gridDim{1, 1, 1};
 inline thread_local int t_wave_epoch = 0;  // wave barriers this thread has passed
 
 inline unsigned char* lds_base() { return g_block->lds; }
+
+// Cross-workgroup checker over global memory (enabled by EMU_TRACK_GLOBAL=1;
+// accesses made through buffer loads / stores and the in-place path's xld /
+// xst): within one launch, every 8-byte word remembers the workgroup that
+// wrote it and the one that read it (-2: several); a word written by one
+// workgroup and read or written by another is a cross-workgroup hazard --
+// workgroups run in no defined order on the GPU.
+struct gword {
+    int w = -1, r = -1;
+};
+inline std::mutex g_gmu;
+inline std::unordered_map<uintptr_t, gword> g_gwords;
+inline std::atomic<long> g_global_races{0};
+inline bool g_track = std::getenv("EMU_TRACK_GLOBAL") && std::atoi(std::getenv("EMU_TRACK_GLOBAL")) != 0;
+inline thread_local int t_block_id = 0;
+
+inline void global_touch(const void* p, size_t bytes, bool write) {
+    if (!g_track) return;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(p) & ~uintptr_t(7);
+    const uintptr_t a1 = reinterpret_cast<uintptr_t>(p) + bytes;
+    const int b = t_block_id;
+    std::lock_guard<std::mutex> g(g_gmu);
+    for (uintptr_t a = a0; a < a1; a += 8) {
+        gword& s = g_gwords[a];
+        bool bad;
+        if (write) {
+            bad = (s.w >= 0 && s.w != b) || (s.r != -1 && s.r != b);
+            s.w = b;
+        } else {
+            bad = s.w >= 0 && s.w != b;
+            s.r = s.r == -1 || s.r == b ? b : -2;
+        }
+        if (bad && g_global_races.fetch_add(1) < 8)
+            std::fprintf(stderr, "emu: global word %#lx %s by workgroup %d, touched by workgroup %d/%d\n",
+                         (unsigned long)a, write ? "written" : "read", b, s.w, s.r);
+    }
+}
 
 inline void lds_touch(const void* p, size_t bytes, bool write) {
     block_state* b = g_block;
@@ -158,6 +196,7 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 inline T buf_load(rsrc r, int vo, int so) {
     check_range(r, (long long)vo + so, (int)sizeof(T));
+    global_touch(r.base + vo + so, sizeof(T), false);
     T v;
     std::memcpy(&v, r.base + vo + so, sizeof(T));
     return v;
@@ -165,6 +204,7 @@ inline T buf_load(rsrc r, int vo, int so) {
 template <typename T>
 inline void buf_store(T v, rsrc r, int vo, int so) {
     check_range(r, (long long)vo + so, (int)sizeof(T));
+    global_touch(r.base + vo + so, sizeof(T), true);
     std::memcpy(const_cast<char*>(r.base) + vo + so, &v, sizeof(T));
 }
 
@@ -193,6 +233,7 @@ void launch(void (*k)(P...), dim3 grid, dim3 block, size_t shmem, hipStream_t, A
         std::abort();
     }
     const unsigned nt = block.x, nw = (nt + 63) / 64;
+    if (g_track) g_gwords.clear();  // hazards are within one launch
     for (unsigned bz = 0; bz < grid.z; ++bz)
         for (unsigned by = 0; by < grid.y; ++by)
             for (unsigned bx = 0; bx < grid.x; ++bx) {
@@ -214,6 +255,7 @@ void launch(void (*k)(P...), dim3 grid, dim3 block, size_t shmem, hipStream_t, A
                     th.emplace_back([&, t] {
                         t_threadIdx = {t, 0, 0};
                         t_blockIdx = {bx, by, bz};
+                        t_block_id = (int)(bx + grid.x * (by + grid.y * bz));
                         t_blockDim = block;
                         t_gridDim = grid;
                         k(static_cast<P>(args)...);

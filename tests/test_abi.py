@@ -96,13 +96,14 @@ def test_create_many_validation(lib):
     assert rc == _lib.ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("kw", [dict(n=1024, flags=8), dict(n=4096, variant=2, flags=8),
+@pytest.mark.parametrize("kw", [dict(n=1024, flags=8), dict(n=4096, variant=3, flags=8),
                                 dict(n=4096, variant=1, flags=8), dict(n=4096, dtype=2, flags=8),
                                 dict(n=1 << 17, dtype=0, flags=8), dict(n=4096, flags=12)])
 def test_force_large_validation(lib, kw):
-    """The large-N path can be forced only where it exists (variants 4 and 8,
-    N >= 2^11, FP64 / FP32 storage below 2^15) and not with the multi-pass
-    force flag; the refusal happens before any HIP call."""
+    """The large-N paths can be forced only where they exist (variants 4, 8
+    and their transposed programs 2, 6; N >= 2^11, FP64 / FP32 storage below
+    2^15) and not with the multi-pass force flag; the refusal happens before
+    any HIP call."""
     n = kw.pop("n")
     rc, h = _create(lib, n, **kw)
     assert rc == _lib.ERR_UNSUPPORTED
@@ -179,3 +180,26 @@ def test_fixed_point_not_for_many_or_real(lib):
         == _lib.ERR_UNSUPPORTED
     assert lib.amqft_plan_create_real(ctypes.byref(h), 256, 1, 0, 1, _lib.C32I, 0) == _lib.ERR_UNSUPPORTED
     assert lib.amqft_exec_noalloc(256, 1, 1, _lib.C32I, 0, None, None, None) == _lib.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("n,variant,dtype,flags", [(1 << 15, 1, 1, 32), (1 << 15, 2, 1, 32), (1 << 18, 4, 1, 32),
+                                                   (1 << 15, 4, 2, 32), (1 << 17, 8, 0, 32), (1 << 10, 4, 0, 32 | 8),
+                                                   (1 << 12, 4, 1, 32 | 4), (1 << 10, 4, 1, 32 | 8),
+                                                   (1 << 15, 5, 1, 32), (1 << 16, 3, 0, 32)])
+def test_in_place_validation(lib, n, variant, dtype, flags):
+    """Above one workgroup's LDS the in-place flag exists for variants 4 and 8
+    with FP32 storage at 2^15 .. 2^17 (FP64 2^14 .. 2^16, forced from 2^11)
+    and not with the multi-pass force flag; elsewhere plan creation refuses
+    it before any HIP call."""
+    rc, h = _create(lib, n, variant=variant, dtype=dtype, flags=flags)
+    assert rc == _lib.ERR_UNSUPPORTED
+    assert not h.value
+
+
+def test_in_place_not_for_many_or_real(lib):
+    import numpy as np
+    h = ctypes.c_void_p(3)
+    L = np.array([256, 256], dtype=np.int64)
+    O = np.array([0, 256, 512], dtype=np.int64)
+    assert lib.amqft_plan_create_many(ctypes.byref(h), 2, L.ctypes.data, O.ctypes.data, 4, 1, 32) == _lib.ERR_UNSUPPORTED
+    assert lib.amqft_plan_create_real(ctypes.byref(h), 256, 1, 0, 4, 1, 32) == _lib.ERR_UNSUPPORTED

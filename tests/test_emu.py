@@ -77,6 +77,55 @@ def test_kernel_source_on_cpu(emu_exe, tmp_path, path, variant, dtype, logn, bat
     assert rel(y, ref) <= b, (rel(y, ref), b)
 
 
+# In-place large path: (variant, dtype, log2 N, batch, conjugated).  2^13 and
+# 2^14 have two and four chain workgroups a signal; 16 signals in chunks of 15
+# with the XCD remap of the chain kernel.
+IP_CASES = [(4, 0, 13, 2, 0), (8, 0, 12, 1, 1), (4, 1, 12, 3, 0), (8, 0, 11, 16, 1), (4, 0, 14, 1, 0)]
+
+
+def _run_emu(exe, tmp_path, path, variant, dtype, logn, batch, conj, x, track=True):
+    fin, fout = str(tmp_path / "in.bin"), str(tmp_path / ("out_%s.bin" % path))
+    x.tofile(fin)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    if track:
+        env["EMU_TRACK_GLOBAL"] = "1"
+    r = subprocess.run([exe, path, str(variant), str(dtype), str(logn), str(batch), str(conj), fin, fout],
+                       capture_output=True, text=True, timeout=600, env=env)
+    y = np.fromfile(fout, dtype=x.dtype).reshape(x.shape) if r.returncode == 0 else None
+    return r, y
+
+
+@pytest.mark.parametrize("variant,dtype,logn,batch,conj", IP_CASES)
+def test_in_place_large_path(emu_exe, tmp_path, variant, dtype, logn, batch, conj):
+    """The in-place form of the large-N path keeps the rows in the signal's own
+    buffer: no workgroup may read or write a word that another workgroup of
+    the same launch writes (checked on every access to the signal), and the
+    result is the out-of-place path's, bit for bit (same operations, same
+    order), within the variant's pin of the exact DFT."""
+    n = 1 << logn
+    x = inputs.complex_normal(7 + logn, batch, n).astype(np.complex128 if dtype == 0 else np.complex64)
+    r_ip, y_ip = _run_emu(emu_exe, tmp_path, "large_ip", variant, dtype, logn, batch, conj, x)
+    assert r_ip.returncode == 0, r_ip.stderr[-4000:]
+    r, y = _run_emu(emu_exe, tmp_path, "large", variant, dtype, logn, batch, conj, x)
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert np.array_equal(y_ip, y)
+    src = np.conj(x) if conj else x
+    ref = truth(src)
+    b = bound(variant, dtype == 0, src, ref)
+    if conj:
+        ref = np.conj(ref)
+    assert rel(y_ip, ref) <= b, (rel(y_ip, ref), b)
+
+
+def test_in_place_checker_rejects_a_layout_that_ignores_the_readers(emu_exe, tmp_path):
+    """The cross-workgroup checker's own test: with every slot left in its own
+    orbit (no ownership, nothing shared) chain workgroups overwrite rows that
+    other chain workgroups still read."""
+    x = inputs.complex_normal(20, 2, 1 << 13)
+    r, _ = _run_emu(emu_exe, tmp_path, "large_ip_naive", 4, 0, 13, 2, 0, x)
+    assert r.returncode == 5 and "cross-workgroup hazards" in r.stderr, (r.returncode, r.stderr[-2000:])
+
+
 # The depth-6 split of the transposed large path (N >= 2^18) takes about
 # three minutes here; AMQFT_EMU_DEEP=1 adds it.
 DUAL_CASES = [("tkernel", 2, 12), ("tkernel", 6, 9), ("tkernel", 2, 8), ("tkernel", 6, 8),
