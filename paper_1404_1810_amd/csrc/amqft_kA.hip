@@ -541,33 +541,28 @@ __global__ __launch_bounds__(256) void amqft_kL_rback(const cx<R>* __restrict__ 
 // count as zero) give harmonics 8j .. 8j + 7 of depth-0 block a of both sides.
 // B0 (levels 2..0) of the group of depth-3 slot p of the sixteen rows: the
 // eight harmonics per side it expands to.  ld(r, s) reads slot s of row
-// (side, q) = r / 8, r % 8.  COND: read the neighbour slots only where the
-// group has neighbours in its block (the in-place path, whose slots past a
-// block's ends may belong to another workgroup); otherwise read them always
-// and discard.
-template <int V, typename R, int LOGN, bool COND = false, typename LD>
+// (side, q) = r / 8, r % 8.  The neighbour slots p - 1, p + 1 are read always
+// and discarded where the group has no neighbour in its block; OWN: such a
+// discarded read goes to slot p instead (the in-place path, whose slots past
+// a block's ends may belong to another workgroup).
+template <int V, typename R, int LOGN, bool OWN = false, typename LD>
 __device__ __forceinline__ void b0_group(LD&& ld, int p, cx<R> (&o)[2][8]) {
     constexpr int N = 1 << LOGN, W3 = N / 16, LW3 = ilog2c(W3);
     const int a = __clz(~(p << (32 - LW3)));  // block of position p in the row's block layout
     const int j = p - (W3 - (W3 >> a));
     const int sp = W3 >> (a + 1);
-    const int pm = p > 0 ? p - 1 : 0;
+    const int pm = OWN ? (j >= 1 ? p - 1 : p) : (p > 0 ? p - 1 : 0);
+    const int pp = OWN ? (j + 1 < sp ? p + 1 : p) : p + 1;
     cx<R> ext[2][8][3];
 #pragma unroll
     for (int side = 0; side < 2; ++side)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int r = side * 8 + q;
-            if constexpr (COND) {
-                ext[side][q][0] = j >= 1 ? ld(r, p - 1) : zero<R>();
-                ext[side][q][1] = ld(r, p);
-                ext[side][q][2] = j + 1 < sp ? ld(r, p + 1) : zero<R>();
-            } else {
-                const cx<R> lm = ld(r, pm), lp = ld(r, p + 1);
-                ext[side][q][0] = j >= 1 ? lm : zero<R>();
-                ext[side][q][1] = ld(r, p);
-                ext[side][q][2] = j + 1 < sp ? lp : zero<R>();
-            }
+            const cx<R> lm = ld(r, pm), lp = ld(r, pp);
+            ext[side][q][0] = j >= 1 ? lm : zero<R>();
+            ext[side][q][1] = ld(r, p);
+            ext[side][q][2] = j + 1 < sp ? lp : zero<R>();
         }
     bwd_run<V, 0, 3, R>(ext[0], o[0]);
     bwd_run<V, 1, 3, R>(ext[1], o[1]);
@@ -611,7 +606,8 @@ __global__ __launch_bounds__(64) void amqft_kL_back(const cx<R>* __restrict__ ws
 // at H/8 - H/2^a), the fourteen groups -> the one value of each that thread
 // k0 = 0 reads (DCT side at element 0 of the even groups, DST side at element
 // 7 of the odd ones) at ws2 + N/8; and the slots that two workgroups of the
-// chain kernel read, 16 rows each, -> ws3.
+// chain kernel read -> ws3, row-major (row r of shared slot k at r nsh + k, so
+// that neighbouring shared slots are neighbouring words).
 template <int V, typename R, int LOGN>
 __global__ __launch_bounds__(64) void amqft_kL_back_ip(const cx<R>* x, cx<R>* __restrict__ ws2,
                                                         cx<R>* __restrict__ ws3, const int* __restrict__ iptab,
@@ -627,7 +623,7 @@ __global__ __launch_bounds__(64) void amqft_kL_back_ip(const cx<R>* x, cx<R>* __
     if (i >= NB3 + 14) {
         const int k = i - NB3 - 14, q = iptab[2 * W3 + k];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) ws3[(sl * nsh + k) * 16 + r] = ld(r, q);
+        for (int r = 0; r < 16; ++r) ws3[(sl * 16 + r) * nsh + k] = ld(r, q);
         return;
     }
     int p, y = 0;
@@ -713,10 +709,13 @@ __device__ __forceinline__ void kL_bchain_body(const cx<typename storage<S>::R>*
                 const long long gsb = gs * (long long)N;
                 const int* orb = iptab;
                 const int* shx = iptab + W3;
+                // one load a row through the selected address (no branch
+                // around loads: those would wait for each other)
                 b0_group<V, R, LOGN, true>(
                     [&](int r, int q) {
-                        const int x = shx[q];
-                        return x >= 0 ? ws3[(sl * nsh + x) * 16 + r] : xld(ws1 + gsb + ip_member<LOGN>(r, orb[q]));
+                        const int x = shx[q], ob = orb[q];
+                        const cx<R>* src = x >= 0 ? ws3 + (sl * 16 + r) * nsh + x : ws1 + gsb + ip_member<LOGN>(r, ob);
+                        return xld(src);
                     },
                     W3 - (W3 >> a) + g, o);
             } else {
