@@ -508,8 +508,8 @@ def bench_fixed(args, stream):
 def bench_inplace(args, stream):
     """The large-N path in place against out of place: 256 signals of 2^16
     points (FP32, variant 4, 512 MiB), the same inputs, default workspaces;
-    time per launch, workspace bytes, and whether the outputs agree bit for
-    bit (same operations in the same order)."""
+    time per launch, workspace bytes, and the relative distance of the two
+    outputs."""
     import ctypes
 
     import torch
@@ -544,7 +544,10 @@ def bench_inplace(args, stream):
         log("large path %s: avg %.4f ms, %.1f GB/s algorithmic, workspace %.1f MiB"
             % (name, r["avg_ms"], algo / r["avg_ms"] / 1e6, ws.value / 2 ** 20))
         plan.close()
-    res["bit_identical"] = bool(torch.equal(outs["in_place"], outs["out_of_place"]))
+    # the same operations in the same order; the compiler contracts the two
+    # kernel instantiations into FMAs differently, so they agree to rounding
+    d = torch.linalg.vector_norm(outs["in_place"] - outs["out_of_place"])
+    res["rel_l2_in_place_vs_out_of_place"] = float(d / torch.linalg.vector_norm(outs["out_of_place"]))
     return {"workload": "batch %d x N=%d complex64, re/im N(0,1) seed %d, variant %d, forward" % (B, n, seed, v),
             **res}
 
@@ -568,8 +571,9 @@ def main():
     ap.add_argument("--kernel-desc", default="", help="kernel description for --ingest-pmc")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the FP64, uneven-batch and fused-gradient workloads")
-    ap.add_argument("--workload", default="headline", choices=["headline", "precision"],
-                    help="precision: the 2^20-point FP16 accuracy/throughput study instead")
+    ap.add_argument("--workload", default="headline", choices=["headline", "precision", "inplace"],
+                    help="precision: the 2^20-point FP16 accuracy/throughput study instead; inplace: only the "
+                         "in-place against out-of-place large-N workload")
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(args, *args.ingest_pmc)
@@ -591,6 +595,13 @@ def main():
                           "n_gpus": 1, "data": "synthetic", "dtype": "f16 / bf16 storage, f32 arithmetic",
                           "config": {"workload": res["workload"]}, "variants": res["variants"],
                           "sampled_signals": res["sampled_signals"]}), flush=True)
+        return
+
+    if args.workload == "inplace":
+        res = bench_inplace(args, torch.cuda.current_stream())
+        print(json.dumps({"metric": "in-place vs out-of-place large-N AM-QFT: ms per launch and workspace bytes",
+                          "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+                          "config": {"workload": res.pop("workload")}, **res}), flush=True)
         return
 
     n, batch = args.n, args.batch
