@@ -160,14 +160,47 @@ __global__ __launch_bounds__(256) void mp_level_kernel(const cx<R>* __restrict__
 
 // ---------------------------------------------------------------------------
 // recurrences of M1/M5 (skeleton A backward) and M3/M7 (skeleton B forward)
-// over the hi halves of the active big sub-blocks: one workgroup per segment
+// over the hi halves of the active big sub-blocks: one workgroup per segment.
+// Y_r = a_r + c Y_{r-1} along the recurrence direction (c = +-1) in tiles of
+// 256 K values: coalesced loads into LDS, K consecutive values a thread,
+// the carries of the threads by a workgroup prefix sum (K is even, so a
+// chunk's carry passes through with weight c^K = 1), coalesced stores from
+// LDS; the last value of a tile carries into the next.
 // ---------------------------------------------------------------------------
+constexpr int kScanK = 8, kScanT = 256;
+
+// exclusive prefix sum of v over the workgroup's 256 threads; total: the sum
+template <typename R>
+__device__ __forceinline__ cx<R> wg_excl_sum(cx<R> v, cx<R>* wsum, int tid, cx<R>& total) {
+    const int lane = tid & 63, wave = tid >> 6;
+    cx<R> incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const cx<R> u = shfl_up_cx(incl, d);
+        if (lane >= d) incl = incl + u;
+    }
+    if (lane == 63) stc(wsum + wave, incl);
+    __syncthreads();
+    cx<R> before = {R(0), R(0)}, all = {R(0), R(0)};
+#pragma unroll
+    for (int w = 0; w < kScanT / 64; ++w) {
+        const cx<R> t = ldc(wsum + w);
+        if (w < wave) before = before + t;
+        all = all + t;
+    }
+    __syncthreads();
+    total = all;
+    return before + incl - v;
+}
+
 template <int V, bool SKEL_A, typename R>
-__global__ __launch_bounds__(256) void mp_scan_kernel(const cx<R>* __restrict__ src, cx<R>* __restrict__ tmp,
-                                                      int logn, int sb, int lev, int nseg_side) {
+__global__ __launch_bounds__(kScanT) void mp_scan_kernel(const cx<R>* __restrict__ src, cx<R>* __restrict__ tmp,
+                                                         int logn, int sb, int lev, int nseg_side) {
     constexpr R c = R(variant_traits<V>::sign);
     constexpr bool SW = variant_traits<V>::switches;
-    __shared__ cx<R> scr[256];
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<R>* tile = reinterpret_cast<cx<R>*>(smem);  // kScanT * kScanK values, then the wave sums
+    cx<R>* wsum = tile + kScanT * kScanK;
     const int N = 1 << logn, H = N >> 1, D = logn - 2;
     const long long sig = blockIdx.y;
     int sidx = blockIdx.x;
@@ -185,33 +218,43 @@ __global__ __launch_bounds__(256) void mp_scan_kernel(const cx<R>* __restrict__ 
     if (SKEL_A) fwd = (V == 1) ? (sigma == 0) : (sigma != 0);
     else fwd = (V == 3) ? (sigma != 0) : (sigma == 0);
     const bool dctc = (sigma == 0);
-    auto val = [&](int i) -> cx<R> {
-        if (SKEL_A) return x[base + h + i];
-        return x[base + (dctc ? 2 * i + 1 : 2 * i)];
-    };
-    const int T = (int)blockDim.x < h / 2 ? (int)blockDim.x : h / 2;  // threads with a chunk
-    const int chunk = h / T;  // even, >= 2
-    const int tid = threadIdx.x;
-    const bool part = tid < T;
-    // position order along the recurrence direction
+    // position of the r-th value along the recurrence direction
     auto idx = [&](int r) { return fwd ? r : h - 1 - r; };
-    const int r0 = tid * chunk;
-    cx<R> Y = {R(0), R(0)};
-    for (int r = r0; part && r < r0 + chunk; ++r) {
-        cx<R> a = val(idx(r));
-        if (SKEL_A && r == 0) a = a * R(0.5);
-        Y = a + Y * c;
-    }
-    const cx<R> carry = chunk_carry(scr, tid, Y, part, true, T);
-    Y = carry;
-    for (int r = r0; part && r < r0 + chunk; ++r) {
+    auto val = [&](int r) -> cx<R> {
         const int i = idx(r);
-        cx<R> a = val(i);
+        cx<R> a = SKEL_A ? x[base + h + i] : x[base + (dctc ? 2 * i + 1 : 2 * i)];
         if (SKEL_A && r == 0) a = a * R(0.5);
-        Y = a + Y * c;
-        cx<R> o = Y;
-        if (!SKEL_A && r == h - 1) o = o * R(0.5);
-        y[base + h + i] = o;
+        return a;
+    };
+    const int tid = threadIdx.x;
+    const int K = h < kScanK ? h : kScanK;           // values a thread (even: h >= 2)
+    const int TS = h < kScanT * K ? h : kScanT * K;  // values a tile
+    cx<R> carry = {R(0), R(0)};                     // Y before the tile
+    for (int t0 = 0; t0 < h; t0 += TS) {
+        for (int u = tid; u < TS; u += kScanT) stc(tile + u, val(t0 + u));
+        __syncthreads();
+        const bool part = tid * K < TS;
+        cx<R> Y = {R(0), R(0)};
+        if (part)
+            for (int k = 0; k < K; ++k) Y = ldc(tile + tid * K + k) + Y * c;
+        cx<R> total;
+        const cx<R> before = wg_excl_sum(part ? Y : cx<R>{R(0), R(0)}, wsum, tid, total);
+        if (part) {
+            Y = carry + before;
+            for (int k = 0; k < K; ++k) {
+                Y = ldc(tile + tid * K + k) + Y * c;
+                stc(tile + tid * K + k, Y);
+            }
+        }
+        carry = carry + total;
+        __syncthreads();
+        for (int u = tid; u < TS; u += kScanT) {
+            const int r = t0 + u;
+            cx<R> o = ldc(tile + u);
+            if (!SKEL_A && r == h - 1) o = o * R(0.5);
+            y[base + h + idx(r)] = o;
+        }
+        __syncthreads();
     }
 }
 
@@ -366,7 +409,8 @@ hipError_t scan(const cx<R>* a, cx<R>* tmp, int logn, int sb, int lev, long long
     const int active = D - sb - lev;  // big blocks still splitting at this level
     const int nseg_side = active << lev;
     hipLaunchKernelGGL((mp_scan_kernel<V, variant_traits<V>::skel_a, R>), dim3(2 * nseg_side, (unsigned)nsig),
-                       dim3(256), 0, st, a, tmp, logn, sb, lev, nseg_side);
+                       dim3(kScanT), (kScanT * kScanK + kScanT / 64) * sizeof(cx<R>), st, a, tmp, logn, sb, lev,
+                       nseg_side);
     return hipGetLastError();
 }
 

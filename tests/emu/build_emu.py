@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_1404_1810_amd", "csrc")
 OUT_DIR = os.path.join(ROOT, "_build", "emu")
-KERNELS = ["amqft_kA.hip", "amqft_lds.hip", "amqft_fast.hip", "amqft_kB.hip", "amqft_kLT.hip"]
+KERNELS = ["amqft_kA.hip", "amqft_lds.hip", "amqft_fast.hip", "amqft_kB.hip", "amqft_kLT.hip", "amqft_multipass.hip"]
 HEADERS = ["amqft_device.h", "amqft_internal.h", "amqft_levels.h", "amqft_leaf.h", "amqft_kA_passes.h", "amqft_kB_passes.h",
            "amqft_iplayout.h"]
 CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")

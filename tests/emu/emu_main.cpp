@@ -8,13 +8,15 @@
 // that no workgroup touches a word another workgroup of the same launch
 // writes), large_ip_naive (the same with a slot layout that ignores which
 // workgroup reads a slot: the checker's own test), tkernel (the transposed
-// compile-time kernel).  DTYPE 0 = complex FP64, 1 = complex FP32,
+// compile-time kernel), multipass (the multi-pass engine, sub-blocks as a
+// forced plan takes them).  DTYPE 0 = complex FP64, 1 = complex FP32,
 // 4 = complex int32 fixed point (Q2.29 constants).
 // IN / OUT: raw interleaved complex arrays of BATCH x 2^LOGN values.
 // The constant table is built on the host in long double and rounded once.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -94,6 +96,27 @@ int main(int argc, char** argv) {
         k.conj_in = conj;
         k.conj_out = conj;
         e = launch_kL(k, nullptr);
+    } else if (path == "multipass") {
+        // the multi-pass engine with the sub-block size a forced plan takes
+        // (several global levels above it), two chunks when the batch allows
+        mp_launch m{};
+        m.variant = variant;
+        m.dtype = dtype;
+        m.logn = logn;
+        m.sb = std::max(2, std::min(multipass_sb(dtype), logn - 5));
+        m.batch = batch;
+        m.chunk = batch > 1 ? batch - 1 : 1;
+        std::vector<unsigned char> w0((size_t)m.chunk * n * esz), w1(w0.size()), w2(w0.size());
+        m.in = in.data();
+        m.out = out.data();
+        m.ws0 = w0.data();
+        m.ws1 = w1.data();
+        m.ws2 = w2.data();
+        m.ktab = kt.data();
+        m.ktab_log2n = logn;
+        m.conj_in = conj;
+        m.conj_out = conj;
+        e = launch_multipass(m, nullptr);
     } else if (path == "large_ip" || path == "large_ip_naive") {
         kl_launch k{};
         k.variant = variant;

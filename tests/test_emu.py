@@ -35,6 +35,8 @@ CASES = [
     ("lds", 1, 1, 14, 1, 0),     # recurrences across several waves
     ("lds", 5, 0, 9, 3, 1),      # two signals per workgroup, adjoint
     ("lds", 8, 0, 11, 2, 0),
+    ("lds", 4, 1, 10, 40, 1),    # one-wave workgroups, many of them
+    ("lds", 5, 0, 9, 23, 0),     # two signals a workgroup, ragged last one
     ("tkernel", 2, 0, 8, 5, 0),  # amqft_kB_kernel: four signals per workgroup
     ("tkernel", 2, 0, 11, 2, 1),
     ("tkernel", 2, 1, 12, 2, 0),
@@ -53,6 +55,11 @@ CASES = [
     ("large", 2, 1, 12, 2, 0),
     ("large", 2, 0, 13, 1, 1),   # two-walk fold, 4096-point rows
     ("generic", 3, 0, 10, 3, 0),  # level engine
+    ("multipass", 1, 0, 10, 3, 0),  # multi-pass engine: global recurrence scans (skeleton A), LDS sub-blocks
+    ("multipass", 3, 0, 11, 2, 1),  # ... skeleton B, adjoint, two chunks
+    ("multipass", 5, 0, 9, 3, 0),
+    ("multipass", 7, 0, 10, 2, 0),
+    ("multipass", 4, 1, 11, 2, 0),  # gather levels only
     ("lds", 7, 0, 12, 1, 0),     # amqft_fast_kernel
 ]
 
