@@ -382,3 +382,51 @@ def test_alloc_failure_status(monkeypatch):
     torch.cuda.synchronize()
     x = torch.ones(4, 64, dtype=torch.complex64, device="cuda")  # the device still works
     assert torch.allclose(_api().fft(x, 4)[:, 0], torch.full((4,), 64, dtype=torch.complex64, device="cuda"))
+
+
+def _closed_form_inputs(n):
+    """delta(0), delta(N/2), ones, i delta(0): spectra ones, (-1)^k, N delta(k),
+    i -- exact in the FP32 oracle of every variant at these sizes, because the
+    ill-conditioned constants of variants 5-8 multiply only zeros."""
+    k = np.arange(n)
+    x = np.zeros((4, n), np.complex128)
+    x[0, 0] = 1
+    x[1, n // 2] = 1
+    x[2, :] = 1
+    x[3, 0] = 1j
+    want = np.stack([np.ones(n), (-1.0) ** k, n * (k == 0), 1j * np.ones(n)]).astype(np.complex128)
+    return x, want
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype,n,flags", (("c64", 1 << 15, 0), ("c64", 1 << 17, 0), ("c128", 1 << 15, 0),
+                                           ("c64", 1 << 20, 0), ("c64", 1 << 16, 32), ("c128", 1 << 12, 4)))
+@pytest.mark.parametrize("variant", [5, 6, 7, 8])
+def test_closed_forms_where_random_inputs_have_no_pin(variant, dtype, n, flags):
+    """Variants 5-8 above one workgroup's LDS have no pin for random inputs
+    (their own error in the oracle is of order one or not finite).  Four
+    inputs with closed-form spectra pin every path they take there -- the
+    large-N path (8), its transposed program (6), the multi-pass engine (5,
+    7; also forced), in place where it exists -- to the exact result: a
+    kernel that drops, misplaces or mis-signs any output fails."""
+    api = _api()
+    from paper_1404_1810_amd import _lib
+    if flags == 32 and variant != 8:
+        pytest.skip("in place above LDS: variants 4 and 8")
+    x_np, want = _closed_form_inputs(n)
+    code = _lib.C128 if dtype == "c128" else _lib.C64
+    _say("closed forms variant", variant, dtype, "n", n, "flags", flags)
+    x = torch.from_numpy(x_np.astype(np.complex128 if dtype == "c128" else np.complex64)).cuda()
+    plan = api.Plan(n, 4, variant, code, flags)
+    if flags == 32:
+        plan.exec(x, out=x)
+        y = x
+    else:
+        y = plan.exec(x)
+    torch.cuda.synchronize()
+    plan.close()
+    got = y.cpu().numpy().astype(np.complex128)
+    assert np.all(np.isfinite(got))
+    for row in range(4):
+        e = np.linalg.norm(got[row] - want[row]) / np.linalg.norm(want[row])
+        assert e <= 1e-6, (row, e)
