@@ -121,6 +121,16 @@ int log2_exact(int64_t n) {
 
 int max_lds_log2(int dtype) { return dtype == AMQFT_C128 ? kMaxLdsLog2F64 : kMaxLdsLog2F32; }
 
+// signals per chunk of a path with chunked workspaces: at most cap, and the
+// chunks as equal as they can be (no small last chunk whose launches would
+// be all latency)
+int64_t balanced_chunk(int64_t batch, int64_t cap) {
+    cap = std::max<int64_t>(1, cap);
+    if (batch <= cap) return std::max<int64_t>(1, batch);
+    const int64_t chunks = (batch + cap - 1) / cap;
+    return (batch + chunks - 1) / chunks;
+}
+
 // f(2 pi p / n) for the variant's family (Sec. 7.1), evaluated in long double
 long double family_value_ld(int fam, int64_t p, int64_t n) {
     const long double pi = 3.141592653589793238462643383279502884L;
@@ -527,7 +537,7 @@ amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int varian
             const long mb = atol(env);
             if (mb >= 1 && mb <= (1l << 20)) cap = size_t(mb) << 20;
         }
-        p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per2)));
+        p->chunk = balanced_chunk(batch, (int64_t)(cap / per2));
         p->ws_bytes = (size_t)p->chunk * (per2 + per3 + perc);
         if (batch > 0) {
             e = hipMalloc(&p->ws[1], (size_t)p->chunk * per2);
@@ -545,7 +555,7 @@ amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int varian
             const long mb = atol(env);
             if (mb >= 1 && mb <= (1l << 20)) cap = size_t(mb) << 20;
         }
-        p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per)));
+        p->chunk = balanced_chunk(batch, (int64_t)(cap / per));
         const size_t chain = (size_t)p->chunk * 16 * (dtype == AMQFT_C128 ? 16 : 8);
         p->ws_bytes = 2 * (size_t)p->chunk * per + chain;
         for (int i = 0; i < 3 && batch > 0; ++i) {
@@ -559,7 +569,7 @@ amqft_status create_single(amqft_plan* out, int64_t n, int64_t batch, int varian
                                                      : std::min(multipass_sb(dtype), logn - 3);
         const size_t per = multipass_ws_bytes_per_signal(logn, dtype);
         const size_t cap = size_t(1) << 30;  // bytes per workspace buffer
-        p->chunk = std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)(cap / per)));
+        p->chunk = balanced_chunk(batch, (int64_t)(cap / per));
         p->ws_bytes = 3 * (size_t)p->chunk * per;
         for (int i = 0; i < 3 && batch > 0; ++i) {
             e = hipMalloc(&p->ws[i], (size_t)p->chunk * per);

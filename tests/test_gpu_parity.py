@@ -255,8 +255,8 @@ def _large_case(api, _lib, variant, dtype, n, batch, flags_extra, want_chunk=Non
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("dtype,n,batch,chunk", (("c64", 1 << 15, 5, 4), ("c64", 1 << 17, 3, 1),
-                                                 ("c128", 1 << 14, 5, 4), ("c128", 1 << 15, 3, 2),
+@pytest.mark.parametrize("dtype,n,batch,chunk", (("c64", 1 << 15, 5, 3), ("c64", 1 << 17, 3, 1),
+                                                 ("c128", 1 << 14, 5, 3), ("c128", 1 << 15, 3, 2),
                                                  ("c128", 1 << 16, 2, 1)))
 @pytest.mark.parametrize("variant", [4, 8, 2, 6])
 def test_large_path(variant, dtype, n, batch, chunk, monkeypatch):
