@@ -49,7 +49,7 @@ def _both(api, _lib, variant, dtype, n, batch, flags_extra, adjoint):
     x = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
     pi = api.Plan(n, batch, variant, code, _lib.FLAG_IN_PLACE | flags_extra)
     d = pi.describe()
-    large = flags_extra or n > (1 << (13 if f64 else 14))
+    large = bool(flags_extra & _lib.FLAG_FORCE_LARGE) or n > (1 << (13 if f64 else 14))
     assert ("in place" in d) == bool(large), d
     y_ip = x.clone()
     pi.exec(y_ip, out=y_ip, adjoint=adjoint)
@@ -163,3 +163,17 @@ def test_in_place_large_full_chunk_sampled():
     rows = [0, 31, 63]
     y = x[rows].cpu().numpy()
     xfail_unpinned([assess(y, truth(x_np[rows], 4), 4, False, x_np[rows], "in-place 2^17 sampled")])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant,dtype,n", ((4, "c64", 1 << 15), (8, "c128", 1 << 14)))
+def test_in_place_large_onthefly_constants(variant, dtype, n):
+    """With AMQFT_FLAG_ONTHEFLY_CONSTANTS the in-place path reads the table
+    the device generated; it agrees with the out-of-place path on the same
+    flag to rounding, and (variant 4) with the oracle within the pin."""
+    api = __import__("paper_1404_1810_amd.api", fromlist=["api"])
+    from paper_1404_1810_amd import _lib
+    _say("in-place on-the-fly constants variant", variant, dtype, "n", n)
+    y_ip, y_op, x_np = _both(api, _lib, variant, dtype, n, 3, _lib.FLAG_ONTHEFLY_CONSTANTS, False)
+    _agree(y_ip, y_op, x_np, False)
+    xfail_unpinned([assess(y_ip, truth(x_np, 4), variant, dtype == "c128", x_np, "on-the-fly %s n=%d" % (dtype, n))])
