@@ -187,8 +187,9 @@ amqft_status amqft_plan_create_real(amqft_plan *out, int64_t n, int64_t batch,
  * launch sequence per length class over the same buffer (the classes that
  * need a global workspace on a second stream forked from, and joined back
  * into, `stream`).  The first out-of-place execution autotunes the
- * persistent grid and the multi-pass sub-block sizes (synchronising
- * `stream`); an in-place execution before it runs the default shapes. */
+ * persistent grid, the multi-pass sub-block sizes and the signals per chunk
+ * of the large-N classes (synchronising `stream`); an in-place execution
+ * before it runs the default shapes. */
 amqft_status amqft_plan_create_many(amqft_plan *out, int64_t count,
                                     const int64_t *lengths_host,
                                     const int64_t *offsets_host,

@@ -406,7 +406,8 @@ amqft_status time_it(F fn, hipStream_t s, float* ms) {
 }
 
 // Autotuning of a many-length plan on its first out-of-place execution: the
-// number of persistent workgroups and the sub-block size of each multi-pass
+// number of persistent workgroups, the sub-block size of each multi-pass
+// length class and the chunk (signals per round of kernels) of each large-N
 // length class.  Every candidate computes the same transform, so the
 // buffers hold a valid result whichever candidate ran last.  Results are
 // cached per process and, with AMQFT_TUNE_CACHE set, in that file.
@@ -472,6 +473,36 @@ amqft_status autotune(amqft_plan p, const void* in, void* out, hipStream_t user,
         }
         q->sb = bestsb;
         if (st == AMQFT_OK) tune_put(buf, bestsb);
+    }
+    // large-N classes: signals per chunk (the workspaces were sized for the
+    // largest candidate; smaller chunks keep more of them in the last-level
+    // cache between the kernels, larger ones launch fewer kernels)
+    for (length_class& c : p->classes) {
+        if (st != AMQFT_OK) break;
+        if (!c.sub || !c.sub->large) continue;
+        amqft_plan q = c.sub;
+        snprintf(buf, sizeof buf, "%s/v%d/t%d/large/logn%d/count%lld", arch.c_str(), p->variant, p->dtype, c.logn,
+                 (long long)c.count);
+        const int64_t cap = q->chunk;
+        int ch;
+        if (tune_get(buf, &ch)) {
+            if (ch >= 1 && ch <= cap) q->chunk = ch;
+            continue;
+        }
+        float best = 1e30f;
+        int64_t bestc = cap, prev = 0;
+        for (int d = 1; d <= 4; d *= 2) {
+            const int64_t cand = balanced_chunk(q->batch, cap / d);
+            if (cand == prev) continue;
+            prev = cand;
+            q->chunk = cand;
+            float ms = 0;
+            st = time_it([&] { return exec_single(q, in, out, s, adjoint); }, s, &ms);
+            if (st != AMQFT_OK) break;
+            if (ms < best) { best = ms; bestc = cand; }
+        }
+        q->chunk = bestc;
+        if (st == AMQFT_OK) tune_put(buf, (int)bestc);
     }
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
