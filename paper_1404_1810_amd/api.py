@@ -162,6 +162,25 @@ def adjoint(g: torch.Tensor, variant: int = 4, flags: int = 0, out: torch.Tensor
     return get_plan(n, batch, variant, dt, flags, g.device).exec(g, out=out, adjoint=True)
 
 
+def fft_(x: torch.Tensor, variant: int = 4, flags: int = 0) -> torch.Tensor:
+    """The forward transform in place (AMQFT_FLAG_IN_PLACE: no workspace up to
+    one workgroup's LDS, about a quarter of a signal above it where the
+    in-place path exists; the plan refuses other sizes).  x must be
+    contiguous; it is overwritten and returned."""
+    if not x.is_contiguous():
+        raise ValueError("an in-place transform needs a contiguous tensor")
+    dt, n, batch = _storage(x)
+    return get_plan(n, batch, variant, dt, flags | _lib.FLAG_IN_PLACE, x.device).exec(x, out=x)
+
+
+def adjoint_(g: torch.Tensor, variant: int = 4, flags: int = 0) -> torch.Tensor:
+    """F^H g in place (see fft_)."""
+    if not g.is_contiguous():
+        raise ValueError("an in-place transform needs a contiguous tensor")
+    dt, n, batch = _storage(g)
+    return get_plan(n, batch, variant, dt, flags | _lib.FLAG_IN_PLACE, g.device).exec(g, out=g, adjoint=True)
+
+
 def ifft(X: torch.Tensor, variant: int = 4) -> torch.Tensor:
     """Normalised inverse DFT = F^H X / N (the scaling is the caller's step)."""
     return adjoint(X, variant) / X.shape[-1]

@@ -177,3 +177,24 @@ def test_in_place_large_onthefly_constants(variant, dtype, n):
     y_ip, y_op, x_np = _both(api, _lib, variant, dtype, n, 3, _lib.FLAG_ONTHEFLY_CONSTANTS, False)
     _agree(y_ip, y_op, x_np, False)
     xfail_unpinned([assess(y_ip, truth(x_np, 4), variant, dtype == "c128", x_np, "on-the-fly %s n=%d" % (dtype, n))])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("variant,n,batch", ((4, 1 << 16, 3), (2, 4096, 5), (8, 1 << 15, 2)))
+def test_binding_in_place_forward_and_adjoint(variant, n, batch):
+    """api.fft_ / api.adjoint_ overwrite their argument with the result the
+    out-of-place calls return (to rounding above LDS; the same kernel below)."""
+    from paper_1404_1810_amd import api
+    _say("binding in place variant", variant, "n", n)
+    x_np = inputs.complex_normal(99 + n, batch, n).astype(np.complex64)
+    x = torch.from_numpy(x_np).cuda()
+    want = api.fft(x, variant).cpu().numpy()
+    y = x.clone()
+    r = api.fft_(y, variant)
+    assert r.data_ptr() == y.data_ptr()
+    _agree(y.cpu().numpy(), want, x_np, False)
+    g = x.clone()
+    api.adjoint_(g, variant)
+    _agree(g.cpu().numpy(), api.adjoint(x, variant).cpu().numpy(), x_np, True)
+    with pytest.raises(ValueError):
+        api.fft_(x[:, ::2], variant)
