@@ -198,3 +198,23 @@ def test_binding_in_place_forward_and_adjoint(variant, n, batch):
     _agree(g.cpu().numpy(), api.adjoint(x, variant).cpu().numpy(), x_np, True)
     with pytest.raises(ValueError):
         api.fft_(x[:, ::2], variant)
+
+
+@pytest.mark.gpu
+def test_in_place_empty_batch_and_small_chunks(monkeypatch):
+    """An empty batch does nothing; a 1 MiB workspace runs 9 signals of 2^17
+    points in place in two chunks (N/8 + 16 values of 8 B a signal: 7 fit,
+    so 5 + 4)."""
+    from paper_1404_1810_amd import _lib, api
+    n = 1 << 17
+    _say("in-place empty batch and small chunks")
+    p0 = api.Plan(n, 0, 4, _lib.C64, _lib.FLAG_IN_PLACE)
+    e = torch.empty(0, n, dtype=torch.complex64, device="cuda")
+    p0.exec(e, out=e)
+    p0.close()
+    monkeypatch.setenv("AMQFT_LARGE_WS_MB", "1")
+    p = api.Plan(n, 9, 4, _lib.C64, _lib.FLAG_IN_PLACE)
+    assert "chunk=5" in p.describe(), p.describe()
+    p.close()
+    y_ip, y_op, x_np = _both(api, _lib, 4, "c64", n, 9, 0, False)
+    _agree(y_ip, y_op, x_np, False)
