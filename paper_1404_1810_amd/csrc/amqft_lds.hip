@@ -289,6 +289,7 @@ __global__ __launch_bounds__(256) void amqft_persistent_kernel(const S* __restri
     using VT = variant_traits<V>;
     extern __shared__ __align__(16) unsigned char smem[];
     const bool conj_in = flags & 1, conj_out = flags & 2, onthefly = flags & 4;
+    int kt_logn = -1;  // length whose constants the LDS table holds (items run longest first)
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w4 = items[it];
         const int logn = w4.x, first = w4.y, count = w4.z;
@@ -309,7 +310,9 @@ __global__ __launch_bounds__(256) void amqft_persistent_kernel(const S* __restri
         cx<R>* w = reinterpret_cast<cx<R>*>(smem + kt_bytes) + (size_t)slot * (N + T);
         cx<R>* scr = w + N;
         const long long o = valid ? offsets[first + slot] : 0;
-        load_constants<V, R>(kt, ktab, Q, ktab_log2n - logn, onthefly, logn);
+        // the previous item's last barrier ended every read of the table
+        if (logn != kt_logn) load_constants<V, R>(kt, ktab, Q, ktab_log2n - logn, onthefly, logn);
+        kt_logn = logn;
         load_signal<VT::skel_a, S, R>(w, in + o, ltid, T, D, H, conj_in, valid);
         __syncthreads();
         core<V, R>(w, kt, scr, ltid, T, D, H);
