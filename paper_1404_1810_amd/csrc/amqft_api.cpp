@@ -847,6 +847,7 @@ amqft_status amqft_exec_graph(amqft_plan p, const void* in, void* out, int adjoi
     if (!p) return AMQFT_ERR_INVALID_ARG;
     if ((p->many ? p->count : p->batch) == 0) return AMQFT_OK;
     if (!in || !out) return AMQFT_ERR_INVALID_ARG;
+    if ((p->flags & AMQFT_FLAG_IN_PLACE) && in != out) return AMQFT_ERR_INVALID_ARG;
     hipStream_t user = static_cast<hipStream_t>(stream);
     graph_entry* g = nullptr;
     for (graph_entry& ge : p->graphs)

@@ -218,3 +218,33 @@ def test_in_place_empty_batch_and_small_chunks(monkeypatch):
     p.close()
     y_ip, y_op, x_np = _both(api, _lib, 4, "c64", n, 9, 0, False)
     _agree(y_ip, y_op, x_np, False)
+
+
+@pytest.mark.gpu
+def test_in_place_graph_replays():
+    """The in-place large path captured in a HIP graph (amqft_exec_graph with
+    in == out): every replay, with eager work and synchronisation between,
+    equals the eager in-place result on a fresh copy of the input; a graph
+    execution with distinct buffers is refused before any capture."""
+    from paper_1404_1810_amd import _lib, api
+    n, batch = 1 << 15, 3
+    _say("in-place graph replays")
+    x_np = inputs.complex_normal(31337, batch, n).astype(np.complex64)
+    x0 = torch.from_numpy(x_np).cuda()
+    p = api.Plan(n, batch, 4, _lib.C64, _lib.FLAG_IN_PLACE)
+    ref = x0.clone()
+    p.exec(ref, out=ref)
+    torch.cuda.synchronize()
+    buf = torch.empty_like(x0)
+    for rep in range(3):
+        buf.copy_(x0)
+        torch.cuda.synchronize()
+        api.exec_graph(p, buf, buf)
+        torch.cuda.synchronize()
+        assert torch.equal(buf, ref), rep
+        _ = (x0 * 2).sum().item()  # eager work between the replays
+    other = torch.empty_like(x0)
+    with pytest.raises(_lib.AmqftError):
+        api.exec_graph(p, x0, other)
+    torch.cuda.synchronize()
+    p.close()
