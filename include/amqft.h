@@ -109,9 +109,9 @@ enum {
      * forward transform is unchanged. */
     AMQFT_FLAG_TRANSPOSED_ADJOINT = 16u,
     /* In-place execution (Sec. 7.1: every variant can run in place; an
-     * efficient in-place form is left open there).  amqft_exec /
-     * amqft_exec_adjoint then require in == out (AMQFT_ERR_INVALID_ARG
-     * otherwise).  Up to one workgroup's LDS (2^14 points, 2^13 in FP64) the
+     * efficient in-place form is left open there).  amqft_exec,
+     * amqft_exec_adjoint and amqft_exec_graph then require in == out
+     * (AMQFT_ERR_INVALID_ARG otherwise).  Up to one workgroup's LDS (2^14 points, 2^13 in FP64) the
      * kernels read each signal once and write it once, with no workspace.
      * Above it, variants 4 and 8 with FP32 storage at N = 2^15 .. 2^17 (FP64
      * 2^14 .. 2^16; with AMQFT_FLAG_FORCE_LARGE from 2^11) keep the
