@@ -84,10 +84,12 @@ def test_kernel_source_on_cpu(emu_exe, tmp_path, path, variant, dtype, logn, bat
     assert rel(y, ref) <= b, (rel(y, ref), b)
 
 
-# In-place large path: (variant, dtype, log2 N, batch, conjugated).  2^13 and
-# 2^14 have two and four chain workgroups a signal; 16 signals in chunks of 15
-# with the XCD remap of the chain kernel.
-IP_CASES = [(4, 0, 13, 2, 0), (8, 0, 12, 1, 1), (4, 1, 12, 3, 0), (8, 0, 11, 16, 1), (4, 0, 14, 1, 0)]
+# In-place large path: (variant, dtype, log2 N, batch, conjugated).  2^13,
+# 2^14 and 2^15 have two, four and eight chain workgroups a signal (2^15: a
+# size the path runs at unforced); 16 signals in chunks of 15 with the XCD
+# remap of the chain kernel.
+IP_CASES = [(4, 0, 13, 2, 0), (8, 0, 12, 1, 1), (4, 1, 12, 3, 0), (8, 0, 11, 16, 1), (4, 0, 14, 1, 0),
+            (4, 1, 15, 2, 0)]
 
 
 def _run_emu(exe, tmp_path, path, variant, dtype, logn, batch, conj, x, track=True):
