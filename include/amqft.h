@@ -118,8 +118,8 @@ enum {
      * recursion's intermediate rows in the signal's own buffer: the
      * workspace is about 0.24 N values a signal (the blocks the chain reads
      * at folded indices, N/8 values, and the row slots that two chain
-     * workgroups share) instead of 2 N, and the transform moves as many
-     * bytes as the out-of-place path.  Other variants, sizes and storage
+     * workgroups share) instead of 2 N, and the transform moves the
+     * out-of-place path's bytes plus one copy of those shared slots.  Other variants, sizes and storage
      * types give AMQFT_ERR_UNSUPPORTED above one workgroup's LDS, as do
      * many-length plans. */
     AMQFT_FLAG_IN_PLACE = 32u
