@@ -111,17 +111,18 @@ enum {
     /* In-place execution (Sec. 7.1: every variant can run in place; an
      * efficient in-place form is left open there).  amqft_exec,
      * amqft_exec_adjoint and amqft_exec_graph then require in == out
-     * (AMQFT_ERR_INVALID_ARG otherwise).  Up to one workgroup's LDS (2^14 points, 2^13 in FP64) the
-     * kernels read each signal once and write it once, with no workspace.
-     * Above it, variants 4 and 8 with FP32 storage at N = 2^15 .. 2^17 (FP64
-     * 2^14 .. 2^16; with AMQFT_FLAG_FORCE_LARGE from 2^11) keep the
-     * recursion's intermediate rows in the signal's own buffer: the
-     * workspace is about 0.24 N values a signal (the blocks the chain reads
-     * at folded indices, N/8 values, and the row slots that two chain
-     * workgroups share) instead of 2 N, and the transform moves the
-     * out-of-place path's bytes plus one copy of those shared slots.  Other variants, sizes and storage
-     * types give AMQFT_ERR_UNSUPPORTED above one workgroup's LDS, as do
-     * many-length plans. */
+     * (AMQFT_ERR_INVALID_ARG otherwise).  Up to one workgroup's LDS (2^14
+     * points, 2^13 in FP64) the kernels read each signal once and write it
+     * once, with no workspace.  Above it, variants 4 and 8 with FP32
+     * storage at N = 2^15 .. 2^17 (FP64 2^14 .. 2^16; with
+     * AMQFT_FLAG_FORCE_LARGE from 2^11) keep the recursion's intermediate
+     * rows in the signal's own buffer: the workspace is about 0.24 N values
+     * a signal (the blocks the chain reads at folded indices, N/8 values,
+     * and the row slots that two chain workgroups share) instead of 2 N,
+     * and the transform moves the out-of-place path's bytes plus one copy
+     * of those shared slots.  Other variants, sizes and storage types give
+     * AMQFT_ERR_UNSUPPORTED above one workgroup's LDS, as do many-length
+     * plans. */
     AMQFT_FLAG_IN_PLACE = 32u
 };
 
