@@ -279,19 +279,29 @@ __device__ cx<R> chunk_carry(cx<R>* scr, int ltid, cx<R> total, bool participate
 //   M5 DCT: S(q-1) = E(q)/2, S(k-1) = E(k) + S(k+1) (descending)
 //   M5 DST: S(1) = E(0)/2, S(k+1) = E(k) + S(k-1) (ascending)
 // ---------------------------------------------------------------------------
-template <int V, typename R, typename AD = ad_identity>
+template <int V, typename R, typename AD = ad_identity, int KM = KMAX, bool TOP = false>
 __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, int H, int l, int min_hb = 0) {
     constexpr bool SW = variant_traits<V>::switches;
     constexpr R c = R(variant_traits<V>::sign);
-    const int n2 = 2 << D;
-    cx<R> lo[KMAX], a[KMAX], y[KMAX];
-    bool fwdk[KMAX];
+    // TOP: only the top block of each side (items 2^(D-1) .. 2^D - 1 of the
+    // side), packed onto the threads KM items each
+    const int n2 = TOP ? (1 << D) : (2 << D);
+    auto tmap = [&](int u) {
+        if constexpr (TOP) {
+            const int half = 1 << (D - 1);
+            return ((u >> (D - 1)) << D) + half + (u & (half - 1));
+        } else {
+            return u;
+        }
+    };
+    cx<R> lo[KM], a[KM], y[KM];
+    bool fwdk[KM];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const int t = ltid * KMAX + k;
+    for (int k = 0; k < KM; ++k) {
+        const int t = ltid * KM + k;
         fwdk[k] = true;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW, min_hb);
+            const item it = decode(tmap(t), D, l, H, SW, min_hb);
             if (it.active) {
                 lo[k] = w[AD::at(it.base + it.i)];
                 a[k] = w[AD::at(it.base + it.h + it.i)];
@@ -303,10 +313,10 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
     {
         cx<R> Y = {R(0), R(0)};
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int t = ltid * KMAX + k;
+        for (int k = 0; k < KM; ++k) {
+            const int t = ltid * KM + k;
             if (t < n2) {
-                const item it = decode(t, D, l, H, SW, min_hb);
+                const item it = decode(tmap(t), D, l, H, SW, min_hb);
                 if (it.active && it.h > 1 && fwdk[k]) {
                     cx<R> v = a[k];
                     if (it.i == 0) { Y = {R(0), R(0)}; v = v * R(0.5); }
@@ -317,10 +327,10 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
         }
         Y = {R(0), R(0)};
 #pragma unroll
-        for (int k = KMAX - 1; k >= 0; --k) {
-            const int t = ltid * KMAX + k;
+        for (int k = KM - 1; k >= 0; --k) {
+            const int t = ltid * KM + k;
             if (t < n2) {
-                const item it = decode(t, D, l, H, SW, min_hb);
+                const item it = decode(tmap(t), D, l, H, SW, min_hb);
                 if (it.active && it.h > 1 && !fwdk[k]) {
                     cx<R> v = a[k];
                     if (it.i == it.h - 1) { Y = {R(0), R(0)}; v = v * R(0.5); }
@@ -330,35 +340,35 @@ __device__ void a_bwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
             }
         }
     }
-    // carries across threads (only segments longer than KMAX)
+    // carries across threads (only segments longer than KM)
     int hseg = 0;
     bool act0 = false;
     {
-        const int t = ltid * KMAX;
+        const int t = ltid * KM;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW, min_hb);
+            const item it = decode(tmap(t), D, l, H, SW, min_hb);
             act0 = it.active;
             hseg = it.h;
         }
     }
-    const bool long_seg = act0 && hseg > KMAX;
+    const bool long_seg = act0 && hseg > KM;
     const bool fwd0 = fwdk[0];
-    const cx<R> total = fwd0 ? y[KMAX - 1] : y[0];
-    const int max_tps = ((1 << (D - 1 - l)) / KMAX) > 1 ? (1 << (D - 1 - l)) / KMAX : 1;
-    const cx<R> Yin = chunk_carry(scr, ltid, total, long_seg, fwd0, long_seg ? hseg / KMAX : 1, max_tps);
+    const cx<R> total = fwd0 ? y[KM - 1] : y[0];
+    const int max_tps = ((1 << (D - 1 - l)) / KM) > 1 ? (1 << (D - 1 - l)) / KM : 1;
+    const cx<R> Yin = chunk_carry(scr, ltid, total, long_seg, fwd0, long_seg ? hseg / KM : 1, max_tps);
     if (long_seg) {
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int dist = fwd0 ? k + 1 : KMAX - k;
+        for (int k = 0; k < KM; ++k) {
+            const int dist = fwd0 ? k + 1 : KM - k;
             const R sg = (c < R(0) && (dist & 1)) ? R(-1) : R(1);
             y[k] = y[k] + Yin * sg;
         }
     }
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const int t = ltid * KMAX + k;
+    for (int k = 0; k < KM; ++k) {
+        const int t = ltid * KM + k;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW, min_hb);
+            const item it = decode(tmap(t), D, l, H, SW, min_hb);
             if (it.active) {
                 const int j = it.i;
                 const cx<R> odd = (it.h == 1) ? a[k] : y[k];
@@ -585,19 +595,29 @@ __device__ void b_fwd_level(cx<R>* w, int ltid, int T, int D, int H, int l, int 
 //   M7 DCT: e(2) = s(1), e(n) = s(n-1) + e(n-2) asc., e(q) = [s(q-1) + e(q-2)]/2
 //   M7 DST: e(q-2) = s(q-1), e(n) = s(n+1) + e(n+2) desc., e(0) = [s(1) + e(2)]/2
 // ---------------------------------------------------------------------------
-template <int V, typename R, typename AD = ad_identity>
+template <int V, typename R, typename AD = ad_identity, int KM = KMAX, bool TOP = false>
 __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, int H, int l, int min_hb = 0) {
     constexpr bool SW = variant_traits<V>::switches;
     constexpr R c = R(variant_traits<V>::sign);
-    const int n2 = 2 << D;
-    cx<R> lo[KMAX], a[KMAX], y[KMAX];
-    bool fwdk[KMAX];
+    // TOP: only the top block of each side (items 2^(D-1) .. 2^D - 1 of the
+    // side), packed onto the threads KM items each
+    const int n2 = TOP ? (1 << D) : (2 << D);
+    auto tmap = [&](int u) {
+        if constexpr (TOP) {
+            const int half = 1 << (D - 1);
+            return ((u >> (D - 1)) << D) + half + (u & (half - 1));
+        } else {
+            return u;
+        }
+    };
+    cx<R> lo[KM], a[KM], y[KM];
+    bool fwdk[KM];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const int t = ltid * KMAX + k;
+    for (int k = 0; k < KM; ++k) {
+        const int t = ltid * KM + k;
         fwdk[k] = true;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW, min_hb);
+            const item it = decode(tmap(t), D, l, H, SW, min_hb);
             if (it.active) {
                 const bool dctc = (it.sigma == 0);
                 lo[k] = w[AD::at(it.base + (dctc ? 2 * it.i : 2 * it.i + 1))];
@@ -609,10 +629,10 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
     {
         cx<R> Y = {R(0), R(0)};
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int t = ltid * KMAX + k;
+        for (int k = 0; k < KM; ++k) {
+            const int t = ltid * KM + k;
             if (t < n2) {
-                const item it = decode(t, D, l, H, SW, min_hb);
+                const item it = decode(tmap(t), D, l, H, SW, min_hb);
                 if (it.active && it.h > 1 && fwdk[k]) {
                     if (it.i == 0) Y = {R(0), R(0)};
                     Y = a[k] + Y * c;
@@ -622,10 +642,10 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
         }
         Y = {R(0), R(0)};
 #pragma unroll
-        for (int k = KMAX - 1; k >= 0; --k) {
-            const int t = ltid * KMAX + k;
+        for (int k = KM - 1; k >= 0; --k) {
+            const int t = ltid * KM + k;
             if (t < n2) {
-                const item it = decode(t, D, l, H, SW, min_hb);
+                const item it = decode(tmap(t), D, l, H, SW, min_hb);
                 if (it.active && it.h > 1 && !fwdk[k]) {
                     if (it.i == it.h - 1) Y = {R(0), R(0)};
                     Y = a[k] + Y * c;
@@ -637,31 +657,31 @@ __device__ void b_fwd_scan_level(cx<R>* w, cx<R>* scr, int ltid, int T, int D, i
     int hseg = 0;
     bool act0 = false;
     {
-        const int t = ltid * KMAX;
+        const int t = ltid * KM;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW, min_hb);
+            const item it = decode(tmap(t), D, l, H, SW, min_hb);
             act0 = it.active;
             hseg = it.h;
         }
     }
-    const bool long_seg = act0 && hseg > KMAX;
+    const bool long_seg = act0 && hseg > KM;
     const bool fwd0 = fwdk[0];
-    const cx<R> total = fwd0 ? y[KMAX - 1] : y[0];
-    const int max_tps = ((1 << (D - 1 - l)) / KMAX) > 1 ? (1 << (D - 1 - l)) / KMAX : 1;
-    const cx<R> Yin = chunk_carry(scr, ltid, total, long_seg, fwd0, long_seg ? hseg / KMAX : 1, max_tps);
+    const cx<R> total = fwd0 ? y[KM - 1] : y[0];
+    const int max_tps = ((1 << (D - 1 - l)) / KM) > 1 ? (1 << (D - 1 - l)) / KM : 1;
+    const cx<R> Yin = chunk_carry(scr, ltid, total, long_seg, fwd0, long_seg ? hseg / KM : 1, max_tps);
     if (long_seg) {
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            const int dist = fwd0 ? k + 1 : KMAX - k;
+        for (int k = 0; k < KM; ++k) {
+            const int dist = fwd0 ? k + 1 : KM - k;
             const R sg = (c < R(0) && (dist & 1)) ? R(-1) : R(1);
             y[k] = y[k] + Yin * sg;
         }
     }
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        const int t = ltid * KMAX + k;
+    for (int k = 0; k < KM; ++k) {
+        const int t = ltid * KM + k;
         if (t < n2) {
-            const item it = decode(t, D, l, H, SW, min_hb);
+            const item it = decode(tmap(t), D, l, H, SW, min_hb);
             if (it.active) {
                 cx<R> hi;
                 if (it.h == 1) {

@@ -312,14 +312,16 @@ __global__ __launch_bounds__(1024) void mp_lds_kernel(cx<R>* __restrict__ ws, co
         // only the virtual signal's top block [S, 2S) of each side holds the
         // sub-block; the levels skip the smaller (zero) blocks: at level l
         // that block's sub-blocks have half-size 2^(sb - 1 - l)
+        // (the scan levels give each of the T = 2^(sb-2) threads four of the
+        // top block's 2^sb items, so that every thread has work)
         for (int l = 0; l < Dv; ++l) a_fwd_level<V, R>(w, kt, tid, T, Dv, Hv, l, Dv - 1 - l);
         for (int l = Dv - 1; l >= 0; --l) {
-            if constexpr (VT::recurrence) a_bwd_scan_level<V, R>(w, scr, tid, T, Dv, Hv, l, Dv - 1 - l);
+            if constexpr (VT::recurrence) a_bwd_scan_level<V, R, ad_identity, 4, true>(w, scr, tid, T, Dv, Hv, l, Dv - 1 - l);
             else a_bwd_level<V, R>(w, tid, T, Dv, Hv, l, Dv - 1 - l);
         }
     } else {
         for (int l = 0; l < Dv; ++l) {
-            if constexpr (VT::recurrence) b_fwd_scan_level<V, R>(w, scr, tid, T, Dv, Hv, l, Dv - 1 - l);
+            if constexpr (VT::recurrence) b_fwd_scan_level<V, R, ad_identity, 4, true>(w, scr, tid, T, Dv, Hv, l, Dv - 1 - l);
             else b_fwd_level<V, R>(w, tid, T, Dv, Hv, l, Dv - 1 - l);
         }
         for (int l = Dv - 1; l >= 0; --l) b_bwd_level<V, R>(w, kt, tid, T, Dv, Hv, l, Dv - 1 - l);
